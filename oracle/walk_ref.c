@@ -1,0 +1,508 @@
+/*
+ * walk_ref.c -- plain CPU oracle of the interface Monte Carlo estimate.
+ *
+ * TEST INFRASTRUCTURE.  Only tests/, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this code.  It shares no source with the
+ * HIP library.  It is deliberately plain: scalar loops, one path at a time,
+ * in the order the method states them, built with -ffp-contract=off so that
+ * the only fused multiply-adds are the explicit fma() calls of the
+ * Euler-Maruyama update.
+ *
+ * What is computed (Bihlo & Haynes, Sec. 2.1-2.2):
+ *   The mesh map solves div(w grad x) = 0 on the unit square with Dirichlet
+ *   data x = x_b on the boundary (eq. (5), written for the map from the
+ *   computational square).  Its expanded form (eq. (6)) is
+ *   Laplace(x) + (grad w / w) . grad x = 0, whose Ito diffusion has drift
+ *   grad w / w and diffusion coefficient sqrt(2) (the generator of
+ *   dX = b dt + sigma dW is b.grad + sigma^2/2 Laplace).  The solution is the
+ *   expected boundary value at the first exit (eq. (7a)); each path is
+ *   stepped with Euler-Maruyama and tested for exit at the end of every step
+ *   (Sec. 2.2), and the estimate is the arithmetic mean over N pseudo-random
+ *   paths with standard error O(N^-1/2) (Sec. 2.2).
+ *
+ * Readings where the paper is silent (the same readings bind the HIP path):
+ *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
+ *     counter = (step pair m, path p, node g, 0); step 2m uses words 0,1 and
+ *     step 2m+1 uses words 2,3;
+ *   - uniforms u = ((r >> 9) + 1/2) * 2^-23, exactly representable in both
+ *     float and double; normals by Box-Muller,
+ *     (z_xi, z_eta) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b);
+ *   - exit point: first crossing of the last step's segment with the square
+ *     boundary, in double precision; ties go to xi=0, xi=1, eta=0, eta=1;
+ *   - step cap ceil(t_max / dt); a capped path takes the boundary value at
+ *     the nearest boundary point and is counted.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "sddref.h"
+
+/* ---------------------------------------------------------------- Philox */
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11, Sec. 4):
+ * each round multiplies two counter words by the round multipliers and mixes
+ * the 64-bit products with the other two words and the round key; the key is
+ * advanced by the Weyl constants between rounds. */
+static const uint32_t PHILOX_M0 = 0xD2511F53u;
+static const uint32_t PHILOX_M1 = 0xCD9E8D57u;
+static const uint32_t PHILOX_W0 = 0x9E3779B9u;
+static const uint32_t PHILOX_W1 = 0xBB67AE85u;
+
+void sddref_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void sddref_philox_many(int64_t n, const uint32_t* ctr, const uint32_t key[2], uint32_t* out)
+{
+    for (int64_t i = 0; i < n; ++i) sddref_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
+/* ---------------------------------------------------------------- normals */
+
+static double uniform23(uint32_t r) { return ((double)(r >> 9) + 0.5) * 0x1p-23; }
+
+static void box_muller64(uint32_t ra, uint32_t rb, double* z0, double* z1)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double ua = uniform23(ra), ub = uniform23(rb);
+    double radius = sqrt(-2.0 * log(ua));
+    double angle = two_pi * ub;
+    *z0 = radius * cos(angle);
+    *z1 = radius * sin(angle);
+}
+
+static void box_muller32(uint32_t ra, uint32_t rb, float* z0, float* z1)
+{
+    const float two_pi = 6.28318530717958647692f;
+    float ua = ((float)(ra >> 9) + 0.5f) * 0x1p-23f;
+    float ub = ((float)(rb >> 9) + 0.5f) * 0x1p-23f;
+    float radius = sqrtf(-2.0f * logf(ua));
+    float angle = two_pi * ub;
+    *z0 = radius * cosf(angle);
+    *z1 = radius * sinf(angle);
+}
+
+/* words[n][2] -> z[n][2] (double precision transform) */
+void sddref_normals64(int64_t n, const uint32_t* words, double* z)
+{
+    for (int64_t i = 0; i < n; ++i) box_muller64(words[2 * i], words[2 * i + 1], z + 2 * i, z + 2 * i + 1);
+}
+
+void sddref_uniforms(int64_t n, const uint32_t* words, double* u)
+{
+    for (int64_t i = 0; i < n; ++i) u[i] = uniform23(words[i]);
+}
+
+/* ---------------------------------------------------------------- density */
+
+/* w = base + sum_t amp_t f_t and its gradient (Sec. 2.1: w > 0 is the
+ * diffusion coefficient of eq. (5); the drift of eq. (7b) is grad w / w). */
+static void density64(const ref_density* d, double xi, double eta, double* w, double* gx, double* gy)
+{
+    double W = d->base, Gx = 0.0, Gy = 0.0;
+    for (int t = 0; t < d->n_terms; ++t) {
+        const ref_term* T = &d->term[t];
+        double dx = xi - T->cx, dy = eta - T->cy;
+        switch (T->kind) {
+        case REF_GAUSS: {
+            double e = T->amp * exp(-T->coef * (dx * dx + dy * dy));
+            W += e;
+            Gx += -2.0 * T->coef * dx * e;
+            Gy += -2.0 * T->coef * dy * e;
+        } break;
+        case REF_RING: {
+            double r = sqrt(dx * dx + dy * dy);
+            double e = T->amp * exp(-T->coef * (r - T->r0) * (r - T->r0));
+            W += e;
+            if (r > 0.0) {
+                double g = -2.0 * T->coef * (r - T->r0) * e / r;
+                Gx += g * dx;
+                Gy += g * dy;
+            }
+        } break;
+        case REF_SECH2: {
+            double s = T->coef * (T->nx * dx + T->ny * dy);
+            double sech = 1.0 / cosh(s);
+            double f = T->amp * sech * sech;
+            double dfds = -2.0 * f * tanh(s);
+            W += f;
+            Gx += dfds * T->coef * T->nx;
+            Gy += dfds * T->coef * T->ny;
+        } break;
+        case REF_SIN2: {
+            double s = T->coef * (T->nx * dx + T->ny * dy);
+            double sn = sin(s), cs = cos(s);
+            double dfds = 2.0 * T->amp * sn * cs;
+            W += T->amp * sn * sn;
+            Gx += dfds * T->coef * T->nx;
+            Gy += dfds * T->coef * T->ny;
+        } break;
+        default: break;
+        }
+    }
+    *w = W; *gx = Gx; *gy = Gy;
+}
+
+static void density32(const ref_density* d, float xi, float eta, float* w, float* gx, float* gy)
+{
+    float W = (float)d->base, Gx = 0.0f, Gy = 0.0f;
+    for (int t = 0; t < d->n_terms; ++t) {
+        const ref_term* T = &d->term[t];
+        float amp = (float)T->amp, coef = (float)T->coef;
+        float dx = xi - (float)T->cx, dy = eta - (float)T->cy;
+        switch (T->kind) {
+        case REF_GAUSS: {
+            float e = amp * expf(-coef * (dx * dx + dy * dy));
+            W += e;
+            Gx += -2.0f * coef * dx * e;
+            Gy += -2.0f * coef * dy * e;
+        } break;
+        case REF_RING: {
+            float r = sqrtf(dx * dx + dy * dy);
+            float r0 = (float)T->r0;
+            float e = amp * expf(-coef * (r - r0) * (r - r0));
+            W += e;
+            if (r > 0.0f) {
+                float g = -2.0f * coef * (r - r0) * e / r;
+                Gx += g * dx;
+                Gy += g * dy;
+            }
+        } break;
+        case REF_SECH2: {
+            float nx = (float)T->nx, ny = (float)T->ny;
+            float s = coef * (nx * dx + ny * dy);
+            float sech = 1.0f / coshf(s);
+            float f = amp * sech * sech;
+            float dfds = -2.0f * f * tanhf(s);
+            W += f;
+            Gx += dfds * coef * nx;
+            Gy += dfds * coef * ny;
+        } break;
+        case REF_SIN2: {
+            float nx = (float)T->nx, ny = (float)T->ny;
+            float s = coef * (nx * dx + ny * dy);
+            float sn = sinf(s), cs = cosf(s);
+            float dfds = 2.0f * amp * sn * cs;
+            W += amp * sn * sn;
+            Gx += dfds * coef * nx;
+            Gy += dfds * coef * ny;
+        } break;
+        default: break;
+        }
+    }
+    *w = W; *gx = Gx; *gy = Gy;
+}
+
+/* pts[n][2] -> w[n], grad[n][2] */
+void sddref_density_eval(const ref_density* d, int64_t n, const double* pts, double* w, double* grad)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double gx, gy;
+        density64(d, pts[2 * i], pts[2 * i + 1], &w[i], &gx, &gy);
+        if (grad) { grad[2 * i] = gx; grad[2 * i + 1] = gy; }
+    }
+}
+
+/* ------------------------------------------------------------ boundary map */
+
+/* Dirichlet data on the square boundary (eq. (5)): (x_b, y_b) at a boundary
+ * point E on side `side` (0: xi=0, 1: xi=1, 2: eta=0, 3: eta=1). */
+static void bmap_eval(const ref_bmap* b, int side, double xi, double eta, double* x, double* y)
+{
+    switch (b->kind) {
+    case REF_BMAP_IDENTITY:
+        *x = xi; *y = eta;
+        return;
+    case REF_BMAP_AFFINE:
+        *x = b->p[0] + b->p[1] * xi + b->p[2] * eta;
+        *y = b->p[3] + b->p[4] * xi + b->p[5] * eta;
+        return;
+    case REF_BMAP_ANNULUS: {
+        double rho = b->p[0] + (b->p[1] - b->p[0]) * xi;
+        double th = b->p[2] + (b->p[3] - b->p[2]) * eta;
+        *x = rho * cos(th);
+        *y = rho * sin(th);
+        return;
+    }
+    case REF_BMAP_TABLE: {
+        int n = b->n_per_edge;
+        double s = (side < 2) ? eta : xi;
+        double pos = s * (double)(n - 1);
+        int64_t q = (int64_t)floor(pos);
+        if (q < 0) q = 0;
+        if (q > n - 2) q = n - 2;
+        double frac = pos - (double)q;
+        const double* v = b->table + ((int64_t)side * n + q) * 2;
+        *x = v[0] + frac * (v[2] - v[0]);
+        *y = v[1] + frac * (v[3] - v[1]);
+        return;
+    }
+    default:
+        *x = NAN; *y = NAN;
+    }
+}
+
+void sddref_bmap_eval(const ref_bmap* b, int64_t n, const int32_t* side, const double* pts, double* out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        bmap_eval(b, side[i], pts[2 * i], pts[2 * i + 1], &out[2 * i], &out[2 * i + 1]);
+}
+
+/* ------------------------------------------------------------ exit point */
+
+/* First crossing of the segment P -> Q with the boundary of the unit square,
+ * P strictly inside and Q on or outside (the exit test of Sec. 2.2 has just
+ * fired).  Returns the side; E has that side's coordinate set exactly. */
+int sddref_exit_point(double px, double py, double qx, double qy, double* ex, double* ey)
+{
+    double tbest = INFINITY;
+    int side = -1;
+    if (qx <= 0.0) { double t = (0.0 - px) / (qx - px); if (t < tbest) { tbest = t; side = 0; } }
+    if (qx >= 1.0) { double t = (1.0 - px) / (qx - px); if (t < tbest) { tbest = t; side = 1; } }
+    if (qy <= 0.0) { double t = (0.0 - py) / (qy - py); if (t < tbest) { tbest = t; side = 2; } }
+    if (qy >= 1.0) { double t = (1.0 - py) / (qy - py); if (t < tbest) { tbest = t; side = 3; } }
+    double x = px + tbest * (qx - px);
+    double y = py + tbest * (qy - py);
+    if (x < 0.0) x = 0.0;
+    if (x > 1.0) x = 1.0;
+    if (y < 0.0) y = 0.0;
+    if (y > 1.0) y = 1.0;
+    if (side == 0) x = 0.0;
+    if (side == 1) x = 1.0;
+    if (side == 2) y = 0.0;
+    if (side == 3) y = 1.0;
+    *ex = x; *ey = y;
+    return side;
+}
+
+/* Nearest boundary point of an interior point (capped paths). */
+static int nearest_boundary(double px, double py, double* ex, double* ey)
+{
+    double d[4] = { px, 1.0 - px, py, 1.0 - py };
+    int side = 0;
+    for (int s = 1; s < 4; ++s) if (d[s] < d[side]) side = s;
+    *ex = px; *ey = py;
+    if (side == 0) *ex = 0.0;
+    if (side == 1) *ex = 1.0;
+    if (side == 2) *ey = 0.0;
+    if (side == 3) *ey = 1.0;
+    return side;
+}
+
+/* ------------------------------------------------------------ one path */
+
+typedef struct {
+    double x, y;        /* boundary value at the exit point */
+    double exi, eeta;   /* exit point */
+    int64_t steps;
+    int side;
+    int capped;
+} path_out;
+
+/* proj_mode 0: value at the projected exit point (the method).
+ * proj_mode 1: test mode, the map evaluated at the unprojected overshoot
+ *              point X_{k+1} (only meaningful for identity/affine maps). */
+static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, double eta0,
+                        uint64_t g, uint64_t p, double dt, const uint32_t key[2], int64_t kmax,
+                        int proj_mode, path_out* o)
+{
+    const double s = sqrt(2.0 * dt);
+    double X = xi0, Y = eta0;
+    uint32_t r[4] = { 0, 0, 0, 0 };
+    int64_t k = 0;
+    for (;;) {
+        if (k == kmax) {
+            o->side = nearest_boundary(X, Y, &o->exi, &o->eeta);
+            o->capped = 1;
+            break;
+        }
+        if ((k & 1) == 0) {
+            uint32_t ctr[4] = { (uint32_t)(k >> 1), (uint32_t)p, (uint32_t)g, 0u };
+            sddref_philox4x32_10(ctr, key, r);
+        }
+        uint32_t ra = (k & 1) ? r[2] : r[0];
+        uint32_t rb = (k & 1) ? r[3] : r[1];
+        double zx, zy, w, gx, gy;
+        box_muller64(ra, rb, &zx, &zy);
+        density64(d, X, Y, &w, &gx, &gy);
+        double bx = gx / w, by = gy / w;
+        double Xn = fma(s, zx, fma(bx, dt, X));
+        double Yn = fma(s, zy, fma(by, dt, Y));
+        ++k;
+        if (Xn <= 0.0 || Xn >= 1.0 || Yn <= 0.0 || Yn >= 1.0) {
+            if (proj_mode == 1) {
+                o->exi = Xn; o->eeta = Yn; o->side = -1;
+            } else {
+                o->side = sddref_exit_point(X, Y, Xn, Yn, &o->exi, &o->eeta);
+            }
+            o->capped = 0;
+            break;
+        }
+        X = Xn; Y = Yn;
+    }
+    o->steps = k;
+    bmap_eval(b, o->side < 0 ? 0 : o->side, o->exi, o->eeta, &o->x, &o->y);
+}
+
+static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, double eta0,
+                        uint64_t g, uint64_t p, double dt, const uint32_t key[2], int64_t kmax,
+                        int proj_mode, path_out* o)
+{
+    const float s = (float)sqrt(2.0 * dt);
+    const float dtf = (float)dt;
+    float X = (float)xi0, Y = (float)eta0;
+    uint32_t r[4] = { 0, 0, 0, 0 };
+    int64_t k = 0;
+    for (;;) {
+        if (k == kmax) {
+            o->side = nearest_boundary((double)X, (double)Y, &o->exi, &o->eeta);
+            o->capped = 1;
+            break;
+        }
+        if ((k & 1) == 0) {
+            uint32_t ctr[4] = { (uint32_t)(k >> 1), (uint32_t)p, (uint32_t)g, 0u };
+            sddref_philox4x32_10(ctr, key, r);
+        }
+        uint32_t ra = (k & 1) ? r[2] : r[0];
+        uint32_t rb = (k & 1) ? r[3] : r[1];
+        float zx, zy, w, gx, gy;
+        box_muller32(ra, rb, &zx, &zy);
+        density32(d, X, Y, &w, &gx, &gy);
+        float bx = gx / w, by = gy / w;
+        float Xn = fmaf(s, zx, fmaf(bx, dtf, X));
+        float Yn = fmaf(s, zy, fmaf(by, dtf, Y));
+        ++k;
+        if (Xn <= 0.0f || Xn >= 1.0f || Yn <= 0.0f || Yn >= 1.0f) {
+            if (proj_mode == 1) {
+                o->exi = (double)Xn; o->eeta = (double)Yn; o->side = -1;
+            } else {
+                o->side = sddref_exit_point((double)X, (double)Y, (double)Xn, (double)Yn, &o->exi, &o->eeta);
+            }
+            o->capped = 0;
+            break;
+        }
+        X = Xn; Y = Yn;
+    }
+    o->steps = k;
+    bmap_eval(b, o->side < 0 ? 0 : o->side, o->exi, o->eeta, &o->x, &o->y);
+}
+
+/* ------------------------------------------------------------ estimate */
+
+/* Neumaier's compensated summation. */
+typedef struct { double s, c; } nsum;
+static void nsum_add(nsum* a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double nsum_get(const nsum* a) { return a->s + a->c; }
+
+/*
+ * Interface estimate (eq. (7a) by the arithmetic mean, Sec. 2.2).
+ *
+ * nodes[n][2]       start points, strictly inside the unit square
+ * node_ids[n]       counter word g of each node (NULL: g = list index)
+ * paths, path_begin paths path_begin .. path_begin+paths-1 are walked
+ * mean[n][2], se[n][2]  outputs; sums[n][4] (optional) = sum x, sum y,
+ *                   sum x^2, sum y^2 before division
+ * stats[3]          total steps, total paths, capped paths
+ * per_path[n][paths] optional records
+ * Returns 0, or -1 on invalid arguments.
+ */
+int sddref_interface_estimate(const ref_density* d, const ref_bmap* b, const double* nodes,
+                              const int64_t* node_ids, int64_t n, int64_t paths, int64_t path_begin,
+                              double dt, uint64_t seed, int prec, double t_max, int proj_mode,
+                              double* mean, double* se, double* sums, int64_t* stats,
+                              ref_path_record* per_path, int nthreads)
+{
+    if (n < 1 || paths < 1 || !(dt > 0.0) || !(dt < 1.0) || path_begin < 0) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        double a = nodes[2 * i], c = nodes[2 * i + 1];
+        if (!(a > 0.0 && a < 1.0 && c > 0.0 && c < 1.0)) return -1;
+    }
+    if (!(t_max > 0.0)) t_max = 8.0;
+    const int64_t kmax = (int64_t)ceil(t_max / dt);
+    const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    int64_t tot_steps = 0, tot_capped = 0;
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads) reduction(+ : tot_steps, tot_capped)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        const uint64_t g = node_ids ? (uint64_t)node_ids[i] : (uint64_t)i;
+        nsum sx = { 0, 0 }, sy = { 0, 0 }, sxx = { 0, 0 }, syy = { 0, 0 };
+        for (int64_t j = 0; j < paths; ++j) {
+            const uint64_t p = (uint64_t)(path_begin + j);
+            path_out o;
+            if (prec == REF_FP32)
+                walk_path32(d, b, nodes[2 * i], nodes[2 * i + 1], g, p, dt, key, kmax, proj_mode, &o);
+            else
+                walk_path64(d, b, nodes[2 * i], nodes[2 * i + 1], g, p, dt, key, kmax, proj_mode, &o);
+            nsum_add(&sx, o.x);
+            nsum_add(&sy, o.y);
+            nsum_add(&sxx, o.x * o.x);
+            nsum_add(&syy, o.y * o.y);
+            tot_steps += o.steps;
+            tot_capped += o.capped;
+            if (per_path) {
+                ref_path_record* R = &per_path[i * paths + j];
+                R->exit_xi = o.exi;
+                R->exit_eta = o.eeta;
+                R->steps = o.steps;
+                R->side = o.side;
+                R->capped = o.capped;
+            }
+        }
+        const double N = (double)paths;
+        const double Sx = nsum_get(&sx), Sy = nsum_get(&sy);
+        const double Sxx = nsum_get(&sxx), Syy = nsum_get(&syy);
+        const double mx = Sx / N, my = Sy / N;
+        mean[2 * i] = mx;
+        mean[2 * i + 1] = my;
+        if (se) {
+            if (paths > 1) {
+                double vx = Sxx - N * mx * mx, vy = Syy - N * my * my;
+                se[2 * i] = sqrt((vx > 0.0 ? vx : 0.0) / (N * (N - 1.0)));
+                se[2 * i + 1] = sqrt((vy > 0.0 ? vy : 0.0) / (N * (N - 1.0)));
+            } else {
+                se[2 * i] = 0.0;
+                se[2 * i + 1] = 0.0;
+            }
+        }
+        if (sums) {
+            sums[4 * i] = Sx; sums[4 * i + 1] = Sy; sums[4 * i + 2] = Sxx; sums[4 * i + 3] = Syy;
+        }
+    }
+    if (stats) {
+        stats[0] = tot_steps;
+        stats[1] = n * paths;
+        stats[2] = tot_capped;
+    }
+    return 0;
+}
