@@ -1,0 +1,244 @@
+/*
+ * sdd.h -- C ABI of the MI355X library for stochastic-deterministic domain
+ * decomposition of the linear Winslow mesh generator.
+ *
+ * Method: A. Bihlo and R. D. Haynes, "Parallel stochastic methods for PDE
+ * based grid generation" (arXiv 1310.3435).
+ *
+ *   Problem (Sec. 2.1, eq. (5)): on the computational unit square find the
+ *   mesh map (x, y)(xi, eta) with div(w grad x) = div(w grad y) = 0, w > 0,
+ *   and (x, y) = (x_b, y_b) on the boundary.
+ *   Stochastic representation (eq. (6), (7a), (7b)): x(p) = E[x_b(X_tau)]
+ *   where X starts at p, solves the Ito SDE dX = (grad w / w) dt + sqrt(2) dW
+ *   (drift and diffusion read off the expanded form eq. (6); the generator of
+ *   dX = b dt + s dW is b.grad + s^2/2 Laplace) and tau is the first exit
+ *   time from the square.
+ *   Numerics (Sec. 2.2): Euler-Maruyama with step dt, exit test at the end
+ *   of each step, arithmetic mean over N pseudo-random paths (error
+ *   O(N^-1/2)).
+ *   Decomposition (Sec. 2.1, Fig. 1): the estimate is evaluated only at
+ *   interface points; the interfaces are completed by interpolation
+ *   (Sec. 3.5) and every subdomain is then solved once, independently, by
+ *   centred finite differences (Sec. 3.2).
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" must be device memory of the context's
+ *     GPU (e.g. a torch tensor's data_ptr()); "host" pointers are read
+ *     before the call returns.  The caller owns every buffer; the library
+ *     allocates nothing the caller sees.  Scratch memory comes from a
+ *     caller-provided workspace whose size the matching *_workspace_bytes
+ *     call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue work and return after host-side validation; outputs are
+ *     valid once the stream has been synchronised.
+ *   - Return values: SDD_OK (0); negative values are errors and nothing was
+ *     enqueued; no exception crosses the ABI.  sdd_status_string() names
+ *     them.  A context is not thread-safe; use one per host thread.
+ *   - Arrays of points are [n][2] doubles (xi, eta) or (x, y), row-major.
+ */
+#ifndef SDD_H
+#define SDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SDD_OK = 0,
+    SDD_EINVAL = -1,       /* an argument is out of range or inconsistent */
+    SDD_ENOSPC = -2,       /* the workspace is smaller than required */
+    SDD_EDEVICE = -3,      /* a HIP runtime call failed */
+    SDD_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} sdd_status;
+
+typedef enum { SDD_FP64 = 0, SDD_FP32 = 1 } sdd_precision;
+
+/* Density terms; w = base + sum_t amp_t f_t with amp_t >= 0 and base > 0,
+ * so w >= base > 0 as eq. (5) requires.  With d = (xi - cx, eta - cy) and
+ * s = coef * (nx d_xi + ny d_eta):
+ *   GAUSS  f = exp(-coef |d|^2)
+ *   RING   f = exp(-coef (|d| - r0)^2)       (gradient of |d| taken as 0 at d = 0)
+ *   SECH2  f = sech^2(s)
+ *   SIN2   f = sin^2(s)                                                   */
+typedef enum { SDD_TERM_GAUSS = 0, SDD_TERM_RING = 1, SDD_TERM_SECH2 = 2, SDD_TERM_SIN2 = 3 } sdd_term_kind;
+
+#define SDD_MAX_TERMS 4
+
+typedef struct {
+    int32_t kind; /* sdd_term_kind */
+    int32_t pad;
+    double amp, coef, cx, cy, r0, nx, ny;
+} sdd_density_term;
+
+typedef struct {
+    double base;
+    int32_t n_terms; /* 0 .. SDD_MAX_TERMS */
+    int32_t pad;
+    sdd_density_term term[SDD_MAX_TERMS];
+} sdd_density;
+
+/* Boundary map (x_b, y_b) on the sides of the square:
+ *   IDENTITY  (xi, eta)
+ *   AFFINE    x = p0 + p1 xi + p2 eta, y = p3 + p4 xi + p5 eta
+ *   ANNULUS   rho = p0 + (p1-p0) xi, theta = p2 + (p3-p2) eta,
+ *             (x, y) = rho (cos theta, sin theta)
+ *   TABLE     device table[4][n_per_edge][2] for the sides xi=0, xi=1,
+ *             eta=0, eta=1, sampled at parameter q/(n_per_edge-1) (eta on
+ *             the first two sides, xi on the last two), linear in between.
+ *             sdd_bmap_edge1d_table() fills it with the one-dimensional
+ *             generator data of Sec. 3.2.                                  */
+typedef enum { SDD_BMAP_IDENTITY = 0, SDD_BMAP_AFFINE = 1, SDD_BMAP_ANNULUS = 2, SDD_BMAP_TABLE = 3 } sdd_bmap_kind;
+
+typedef struct {
+    int32_t kind; /* sdd_bmap_kind */
+    int32_t n_per_edge;
+    double p[8];
+    const double* table; /* device, TABLE only */
+} sdd_bmap;
+
+/* Global (nx x ny)-node grid on [0,1]^2, xi_i = i/(nx-1), eta_j = j/(ny-1),
+ * split into sx x sy subdomains of (nx-1)/sx + 1 by (ny-1)/sy + 1 nodes
+ * (both divisions exact, at least 2 cells per subdomain side). */
+typedef struct {
+    int32_t nx, ny, sx, sy;
+} sdd_layout;
+
+/* Walk totals: sum of exit step counts (the exiting step included), paths
+ * walked, paths stopped by the step cap. */
+typedef struct {
+    int64_t steps, paths, capped;
+} sdd_walk_stats;
+
+/* One path's exit (parity mode): exit point, step count, side (0: xi=0,
+ * 1: xi=1, 2: eta=0, 3: eta=1), capped flag. */
+typedef struct {
+    double exit_xi, exit_eta;
+    int64_t steps;
+    int32_t side;
+    int32_t capped;
+} sdd_path_record;
+
+typedef struct sdd_ctx sdd_ctx;
+
+const char* sdd_status_string(int status);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int32_t sdd_version(void);
+
+/* Context bound to HIP device `device`; reads its properties once.
+ * SDD_EINVAL for a bad device index or NULL out. */
+sdd_status sdd_create(int32_t device, sdd_ctx** out);
+void sdd_destroy(sdd_ctx* ctx);
+
+/* ---------------------------------------------------------------- walk ---
+ * Monte Carlo estimate of the mesh map at interface points (eq. (7a) by the
+ * arithmetic mean of Sec. 2.2, paths of eq. (7b) by Euler-Maruyama).
+ *
+ * Random numbers (the paper asks only for parallel pseudo-random numbers,
+ * Sec. 2.2): Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ * (m, p, g, 0) for step pair m of path p of node g (g = index in `nodes`);
+ * steps 2m and 2m+1 take words (0,1) and (2,3).  Uniforms
+ * u = ((r >> 9) + 1/2) 2^-23; normals by Box-Muller,
+ * sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).  Path p is therefore the
+ * same wherever and whenever it is walked.
+ *
+ * Step: X <- X + (grad w / w)(X) dt + sqrt(2 dt) Z in the precision `prec`
+ * (SDD_FP32 walks in float, SDD_FP64 in double).  The path exits at the
+ * first step that ends on or outside the square; its exit point is the
+ * first crossing of that step's segment with the boundary, computed in
+ * double in both modes, and its value is the boundary map there.  A path
+ * still inside after ceil(t_max/dt) steps is capped: it takes the value at
+ * the nearest boundary point and is counted in stats->capped.  Per-node
+ * sums are accumulated in double with compensation.
+ *
+ *   w, bmap      host structs (bmap->table, if any, is device memory)
+ *   nodes        device [n_nodes][2], every point strictly inside (0,1)^2
+ *   paths_per_node  N >= 1; paths path_begin .. path_begin+N-1 are walked
+ *   dt           0 < dt < 1, and ceil(t_max/dt) < 2^31
+ *   t_max        step cap in time units; <= 0 selects 8
+ *   mean         device [n][2]   sum / N
+ *   se           device [n][2] or NULL: sqrt(max(0, S2 - N mean^2) / (N(N-1))),
+ *                0 when N = 1
+ *   sums         device [n][4] or NULL: sum x, sum y, sum x^2, sum y^2
+ *   stats        device sdd_walk_stats or NULL (overwritten)
+ *   per_path     device [n][N] sdd_path_record or NULL
+ *   workspace    device, >= sdd_workspace_bytes(n_nodes, N, prec) bytes
+ * Errors: SDD_EINVAL (bad argument; node positions are checked on the
+ * device side only by the walk itself, which treats a node on or outside the
+ * boundary as exiting at once), SDD_ENOSPC, SDD_EDEVICE. */
+size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec);
+
+sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap,
+                                  const double* nodes, int64_t n_nodes, int64_t paths_per_node,
+                                  int64_t path_begin, double dt, uint64_t seed, int32_t prec, double t_max,
+                                  double* mean, double* se, double* sums, sdd_walk_stats* stats,
+                                  sdd_path_record* per_path, void* workspace, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------- interfaces ---
+ * Interface points of a layout (Sec. 2.1, Fig. 1): the (sx-1)(sy-1)
+ * crosspoints row by row, then k points on every segment of every vertical
+ * interface line (lines left to right, segments bottom to top, points in
+ * increasing eta), then k points on every segment of every horizontal line
+ * (lines bottom to top, segments left to right, increasing xi).
+ * placement 0 (uniform): s_i = a + (b-a) i/(k+1) on segment [a, b];
+ * placement 1 (equidistributed): int_a^{s_i} w ds = i/(k+1) int_a^b w ds,
+ * with the integral by Simpson's rule on 4096 panels and linear inversion
+ * inside a panel (the paper places points from the density, Sec. 3.5).
+ * nodes: device [sdd_layout_node_count(L, k)][2].  w may be NULL for
+ * placement 0. */
+int64_t sdd_layout_node_count(const sdd_layout* L, int32_t k);
+
+sdd_status sdd_layout_nodes(sdd_ctx* ctx, const sdd_layout* L, int32_t k, int32_t placement, const sdd_density* w,
+                            double* nodes, void* stream);
+
+/* One-dimensional edge data (Sec. 3.2: tangential boundary values from the
+ * 1D generator): on each side the tangential coordinate is
+ * int_0^s 1/w / int_0^1 1/w along that side (cumulative Simpson on the
+ * n_per_edge - 1 sample intervals), the normal coordinate the side's value.
+ * table: device [4][n_per_edge][2], n_per_edge >= 3.  Use it as a TABLE
+ * bmap. */
+sdd_status sdd_bmap_edge1d_table(sdd_ctx* ctx, const sdd_density* w, int32_t n_per_edge, double* table,
+                                 void* stream);
+
+/* Interface completion (Sec. 3.5: Monte Carlo at a few points plus
+ * interpolation).  values: device [node_count][2], the estimates at `nodes`
+ * (layout order above).  Every segment is interpolated through (start, its
+ * k points, end) in the segment parameter: interp 0 linear, interp 1
+ * monotone piecewise cubic (Fritsch-Carlson slopes, three-point
+ * shape-preserving end slopes).  Segment ends are crosspoint estimates or,
+ * on the outer boundary, the boundary map.
+ * vert: device [sx-1][ny][2] (the full line xi = a/sx); horiz: device
+ * [sy-1][nx][2] (the full line eta = b/sy).  Either may be NULL when that
+ * direction has no line. */
+sdd_status sdd_fill_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t k, const sdd_bmap* bmap,
+                               const double* nodes, const double* values, int32_t interp, double* vert,
+                               double* horiz, void* stream);
+
+/* ------------------------------------------------------------ subdomains ---
+ * Independent Dirichlet solves of every subdomain (Sec. 2.1: solved once, no
+ * iteration between subdomains).  Discretisation: conservative centred
+ * 5-point stencil (Sec. 3.2 uses centred differences), w at the edge
+ * midpoints, x_P = sum a_nb x_nb / sum a_nb with a_E = w(xi+h/2, eta)/h^2
+ * etc.  Solved by red-black successive over-relaxation until the largest
+ * change of a sweep is <= tol (tol <= 0 selects 1e-13) or max_sweeps
+ * (<= 0 selects 100000) sweeps.
+ * mesh: device [ny][nx][2]; on return the boundary ring holds the map, the
+ * interface lines hold vert/horiz, every subdomain interior its solution.
+ * sweeps (device [sx*sy] int32 or NULL) and resid (device [sx*sy] double or
+ * NULL) report, per subdomain b*sx + a, the sweeps taken and the last
+ * largest change (the larger of the two components). */
+size_t sdd_subdomain_workspace_bytes(const sdd_layout* L);
+
+sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const sdd_layout* L,
+                               const double* vert, const double* horiz, double tol, int32_t max_sweeps,
+                               double* mesh, int32_t* sweeps, double* resid, void* workspace, size_t ws_bytes,
+                               void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDD_H */

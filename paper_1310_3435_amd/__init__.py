@@ -1,0 +1,358 @@
+"""MI355X library for stochastic-deterministic domain decomposition of the
+linear Winslow mesh generator (Bihlo & Haynes, arXiv 1310.3435).
+
+This module is the thin Python binding of ``libsdd.so``: it marshals
+arguments into the C structures of ``include/sdd.h`` and calls the entry
+points of the same names.  Device memory and streams come from PyTorch
+(``torch.cuda`` tensors and the current stream); every step of the method
+runs in the library's HIP kernels.  There is no CPU fallback: without the
+built library or without a GPU the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsdd.so")
+
+SDD_FP64, SDD_FP32 = 0, 1
+PREC = {"fp64": SDD_FP64, "fp32": SDD_FP32}
+TERM = {"gauss": 0, "ring": 1, "sech2": 2, "sin2": 3}
+BMAP = {"identity": 0, "affine": 1, "annulus": 2, "table": 3}
+PLACEMENT = {"uniform": 0, "equidistributed": 1}
+INTERP = {"linear": 0, "pchip": 1}
+MAX_TERMS = 4
+
+
+class SddError(RuntimeError):
+    pass
+
+
+class sdd_density_term(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("amp", C.c_double), ("coef", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("r0", C.c_double), ("nx", C.c_double),
+                ("ny", C.c_double)]
+
+
+class sdd_density(C.Structure):
+    _fields_ = [("base", C.c_double), ("n_terms", C.c_int32), ("pad", C.c_int32),
+                ("term", sdd_density_term * MAX_TERMS)]
+
+
+class sdd_bmap(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_per_edge", C.c_int32), ("p", C.c_double * 8), ("table", C.c_void_p)]
+
+
+class sdd_layout(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("sx", C.c_int32), ("sy", C.c_int32)]
+
+
+class sdd_walk_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("paths", C.c_int64), ("capped", C.c_int64)]
+
+
+PATH_RECORD = np.dtype([("exit_xi", "<f8"), ("exit_eta", "<f8"), ("steps", "<i8"), ("side", "<i4"),
+                        ("capped", "<i4")])
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libsdd.so (built by ``paper_1310_3435_amd/build.py``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise SddError(f"{LIB_PATH} is missing: run paper_1310_3435_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, D, U64, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_uint64, C.c_size_t
+    L.sdd_status_string.restype = C.c_char_p
+    L.sdd_status_string.argtypes = [C.c_int]
+    L.sdd_version.restype = I32
+    L.sdd_create.argtypes = [I32, C.POINTER(P)]
+    L.sdd_create.restype = C.c_int
+    L.sdd_destroy.argtypes = [P]
+    L.sdd_destroy.restype = None
+    L.sdd_workspace_bytes.argtypes = [I64, I64, I32]
+    L.sdd_workspace_bytes.restype = SZ
+    L.sdd_interface_estimate.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), P, I64, I64, I64, D, U64,
+                                         I32, D, P, P, P, P, P, P, SZ, P]
+    L.sdd_interface_estimate.restype = C.c_int
+    L.sdd_layout_node_count.argtypes = [C.POINTER(sdd_layout), I32]
+    L.sdd_layout_node_count.restype = I64
+    L.sdd_layout_nodes.argtypes = [P, C.POINTER(sdd_layout), I32, I32, C.POINTER(sdd_density), P, P]
+    L.sdd_layout_nodes.restype = C.c_int
+    L.sdd_bmap_edge1d_table.argtypes = [P, C.POINTER(sdd_density), I32, P, P]
+    L.sdd_bmap_edge1d_table.restype = C.c_int
+    L.sdd_fill_interfaces.argtypes = [P, C.POINTER(sdd_layout), I32, C.POINTER(sdd_bmap), P, P, I32, P, P, P]
+    L.sdd_fill_interfaces.restype = C.c_int
+    L.sdd_subdomain_workspace_bytes.argtypes = [C.POINTER(sdd_layout)]
+    L.sdd_subdomain_workspace_bytes.restype = SZ
+    L.sdd_subdomain_solve.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), C.POINTER(sdd_layout), P, P,
+                                      D, I32, P, P, P, P, SZ, P]
+    L.sdd_subdomain_solve.restype = C.c_int
+    _lib = L
+    return L
+
+
+EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd_workspace_bytes",
+           "sdd_interface_estimate", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
+           "sdd_fill_interfaces", "sdd_subdomain_workspace_bytes", "sdd_subdomain_solve"]
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SddError(f"{what}: {lib().sdd_status_string(rc).decode()} ({rc})")
+
+
+# ------------------------------------------------------------ marshalling
+
+def make_density(d: dict) -> sdd_density:
+    D = sdd_density()
+    D.base = float(d["base"])
+    terms = d["terms"]
+    if len(terms) > MAX_TERMS:
+        raise SddError(f"at most {MAX_TERMS} density terms")
+    D.n_terms = len(terms)
+    for i, t in enumerate(terms):
+        T = D.term[i]
+        T.kind = TERM[t["kind"]]
+        for f in ("amp", "coef", "cx", "cy", "r0", "nx", "ny"):
+            setattr(T, f, float(t.get(f, 0.0)))
+    return D
+
+
+def make_layout(L: dict) -> sdd_layout:
+    return sdd_layout(int(L["nx"]), int(L["ny"]), int(L["sx"]), int(L["sy"]))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise SddError("no GPU visible: the library runs only on the device")
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise SddError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Bmap:
+    """Boundary map descriptor; a table map keeps its device table alive."""
+
+    def __init__(self, desc: dict, ctx: "Context" = None, density: Optional[dict] = None):
+        self.desc = desc
+        self.s = sdd_bmap()
+        self.table = None
+        kind = desc["kind"]
+        for i, v in enumerate(desc.get("p", [])):
+            self.s.p[i] = float(v)
+        if kind == "edge1d":
+            if ctx is None or density is None:
+                raise SddError("an edge1d map needs the context and the density")
+            self.table = sdd_bmap_edge1d_table(ctx, density, int(desc.get("n_per_edge", 4097)))
+            self.s.kind = BMAP["table"]
+        elif kind == "table":
+            torch = _torch()
+            self.table = torch.as_tensor(np.ascontiguousarray(desc["table"], dtype=np.float64)).cuda()
+            self.s.kind = BMAP["table"]
+        else:
+            self.s.kind = BMAP[kind]
+        if self.table is not None:
+            self.s.n_per_edge = int(self.table.shape[1])
+            self.s.table = self.table.data_ptr()
+
+
+class Context:
+    """Owns an ``sdd_ctx`` bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        _torch()
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().sdd_create(device, C.byref(h)), "sdd_create")
+        self.h = h
+        self._ws = None
+
+    def workspace(self, nbytes: int):
+        """A reusable device workspace of at least nbytes."""
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def close(self):
+        if self.h:
+            lib().sdd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ entry points
+
+def sdd_version() -> int:
+    return int(lib().sdd_version())
+
+
+def sdd_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def sdd_workspace_bytes(n_nodes: int, paths_per_node: int, prec: str = "fp64") -> int:
+    return int(lib().sdd_workspace_bytes(int(n_nodes), int(paths_per_node), PREC[prec]))
+
+
+def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_node: int, dt: float, seed: int,
+                           prec: str = "fp64", t_max: float = 8.0, path_begin: int = 0, want_se: bool = True,
+                           want_sums: bool = False, want_stats: bool = True, per_path: bool = False,
+                           stream=None, out: Optional[dict] = None) -> dict:
+    """Monte Carlo estimate at every node (device tensors in, device tensors out).
+
+    nodes: device float64 [n, 2].  Returns dict with 'mean' [n,2], and as
+    requested 'se' [n,2], 'sums' [n,4], 'stats' (int64 [3]: steps, paths,
+    capped) and 'per_path' (uint8 [n, N, 32] records).  Results are valid
+    after the stream synchronises.  Pass ``out`` (a previous result dict) to
+    reuse its buffers.
+    """
+    torch = _torch()
+    B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, ctx, density)
+    D = make_density(density)
+    n = int(nodes.shape[0])
+    dev = nodes.device
+    f64 = dict(dtype=torch.float64, device=dev)
+    o = out if out is not None else {}
+    if "mean" not in o:
+        o["mean"] = torch.empty((n, 2), **f64)
+        if want_se:
+            o["se"] = torch.empty((n, 2), **f64)
+        if want_sums:
+            o["sums"] = torch.empty((n, 4), **f64)
+        if want_stats:
+            o["stats"] = torch.empty(3, dtype=torch.int64, device=dev)
+        if per_path:
+            o["per_path"] = torch.empty((n, int(paths_per_node), 32), dtype=torch.uint8, device=dev)
+    wsb = sdd_workspace_bytes(n, paths_per_node, prec)
+    ws = ctx.workspace(wsb)
+    rc = lib().sdd_interface_estimate(
+        ctx.h, C.byref(D), C.byref(B.s), _ptr(nodes), n, int(paths_per_node), int(path_begin), float(dt),
+        C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), PREC[prec], float(t_max), _ptr(o["mean"]), _ptr(o.get("se")),
+        _ptr(o.get("sums")), _ptr(o.get("stats")), _ptr(o.get("per_path")), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "sdd_interface_estimate")
+    o["_bmap"] = B
+    return o
+
+
+def path_records(per_path) -> np.ndarray:
+    """Per-path records (device uint8 [n, N, 32]) as a host structured array."""
+    a = per_path.cpu().numpy()
+    return a.view(PATH_RECORD).reshape(a.shape[0], a.shape[1])
+
+
+def sdd_layout_node_count(layout: dict, k: int) -> int:
+    L = make_layout(layout)
+    v = int(lib().sdd_layout_node_count(C.byref(L), int(k)))
+    if v < 0:
+        raise SddError("invalid layout")
+    return v
+
+
+def sdd_layout_nodes(ctx: Context, layout: dict, k: int, placement: str = "uniform",
+                     density: Optional[dict] = None, stream=None):
+    torch = _torch()
+    L = make_layout(layout)
+    n = sdd_layout_node_count(layout, k)
+    nodes = torch.empty((max(n, 1), 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    D = make_density(density) if density is not None else None
+    rc = lib().sdd_layout_nodes(ctx.h, C.byref(L), int(k), PLACEMENT[placement],
+                                C.byref(D) if D is not None else None, _ptr(nodes), _stream(stream))
+    _check(rc, "sdd_layout_nodes")
+    return nodes[:n]
+
+
+def sdd_bmap_edge1d_table(ctx: Context, density: dict, n_per_edge: int = 4097, stream=None):
+    torch = _torch()
+    D = make_density(density)
+    table = torch.empty((4, int(n_per_edge), 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(lib().sdd_bmap_edge1d_table(ctx.h, C.byref(D), int(n_per_edge), _ptr(table), _stream(stream)),
+           "sdd_bmap_edge1d_table")
+    return table
+
+
+def sdd_fill_interfaces(ctx: Context, layout: dict, k: int, bmap, nodes, values, interp: str = "linear",
+                        stream=None, density: Optional[dict] = None) -> Tuple[object, object]:
+    torch = _torch()
+    B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, ctx, density)
+    L = make_layout(layout)
+    f64 = dict(dtype=torch.float64, device=f"cuda:{ctx.device}")
+    vert = torch.empty((max(L.sx - 1, 0), L.ny, 2), **f64)
+    horiz = torch.empty((max(L.sy - 1, 0), L.nx, 2), **f64)
+    rc = lib().sdd_fill_interfaces(ctx.h, C.byref(L), int(k), C.byref(B.s), _ptr(nodes), _ptr(values),
+                                   INTERP[interp], _ptr(vert) if vert.numel() else None,
+                                   _ptr(horiz) if horiz.numel() else None, _stream(stream))
+    _check(rc, "sdd_fill_interfaces")
+    return vert, horiz
+
+
+def sdd_subdomain_workspace_bytes(layout: dict) -> int:
+    L = make_layout(layout)
+    return int(lib().sdd_subdomain_workspace_bytes(C.byref(L)))
+
+
+def sdd_subdomain_solve(ctx: Context, density: dict, bmap, layout: dict, vert, horiz, tol: float = 1e-13,
+                        max_sweeps: int = 100000, stream=None, mesh=None) -> dict:
+    torch = _torch()
+    B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, ctx, density)
+    D = make_density(density)
+    L = make_layout(layout)
+    dev = f"cuda:{ctx.device}"
+    if mesh is None:
+        mesh = torch.empty((L.ny, L.nx, 2), dtype=torch.float64, device=dev)
+    nsub = L.sx * L.sy
+    sweeps = torch.empty(nsub, dtype=torch.int32, device=dev)
+    resid = torch.empty(nsub, dtype=torch.float64, device=dev)
+    wsb = sdd_subdomain_workspace_bytes(layout)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    rc = lib().sdd_subdomain_solve(ctx.h, C.byref(D), C.byref(B.s), C.byref(L),
+                                   _ptr(vert) if vert is not None and vert.numel() else None,
+                                   _ptr(horiz) if horiz is not None and horiz.numel() else None,
+                                   float(tol), int(max_sweeps), _ptr(mesh), _ptr(sweeps), _ptr(resid), _ptr(ws),
+                                   ws.numel(), _stream(stream))
+    _check(rc, "sdd_subdomain_solve")
+    return {"mesh": mesh, "sweeps": sweeps, "resid": resid, "_ws": ws}
+
+
+# ------------------------------------------------------------ pipeline
+
+def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -> dict:
+    """Nodes -> interface estimate -> fill -> subdomain solves, all on the GPU."""
+    dens = cfg["density"]
+    B = Bmap(cfg["bmap"], ctx, dens)
+    L = cfg["layout"]
+    nodes = sdd_layout_nodes(ctx, L, cfg["k"], cfg.get("placement", "uniform"), dens, stream=stream)
+    est = sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
+                                 per_path=per_path, stream=stream)
+    vert, horiz = sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"),
+                                      stream=stream)
+    sol = sdd_subdomain_solve(ctx, dens, B, L, vert, horiz, stream=stream)
+    return {"nodes": nodes, "est": est, "vert": vert, "horiz": horiz, "mesh": sol["mesh"], "sweeps": sol["sweeps"],
+            "resid": sol["resid"], "_keep": (B, sol)}

@@ -1,0 +1,290 @@
+// api.hip -- the extern "C" entry points declared in include/sdd.h.
+//
+// Host-side validation, workspace carving and kernel launches; every step of
+// the path itself runs in the kernels of walk.hip and mesh.hip.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "common.h"
+#include "kernels.h"
+#include "sdd.h"
+
+struct sdd_ctx {
+    int device;
+    int cu_count;
+};
+
+namespace {
+
+using namespace sdd;
+
+bool is_finite(double v) { return isfinite(v) != 0; }
+
+sdd_status check_density(const sdd_density* w)
+{
+    if (!w) return SDD_EINVAL;
+    if (!(w->base > 0.0) || !is_finite(w->base)) return SDD_EINVAL;
+    if (w->n_terms < 0 || w->n_terms > SDD_MAX_TERMS) return SDD_EINVAL;
+    for (int t = 0; t < w->n_terms; ++t) {
+        const sdd_density_term& T = w->term[t];
+        if (T.kind < SDD_TERM_GAUSS || T.kind > SDD_TERM_SIN2) return SDD_EINVAL;
+        if (!(T.amp >= 0.0) || !is_finite(T.amp) || !is_finite(T.coef) || !is_finite(T.cx) || !is_finite(T.cy) ||
+            !is_finite(T.r0) || !is_finite(T.nx) || !is_finite(T.ny))
+            return SDD_EINVAL;
+        if ((T.kind == SDD_TERM_GAUSS || T.kind == SDD_TERM_RING) && !(T.coef >= 0.0)) return SDD_EINVAL;
+    }
+    return SDD_OK;
+}
+
+sdd_status check_bmap(const sdd_bmap* b)
+{
+    if (!b) return SDD_EINVAL;
+    if (b->kind < SDD_BMAP_IDENTITY || b->kind > SDD_BMAP_TABLE) return SDD_EINVAL;
+    if (b->kind == SDD_BMAP_TABLE && (!b->table || b->n_per_edge < 2)) return SDD_EINVAL;
+    for (int i = 0; i < 8; ++i)
+        if (!is_finite(b->p[i])) return SDD_EINVAL;
+    return SDD_OK;
+}
+
+sdd_status check_layout(const sdd_layout* L)
+{
+    if (!L) return SDD_EINVAL;
+    if (L->sx < 1 || L->sy < 1 || L->nx < 3 || L->ny < 3) return SDD_EINVAL;
+    if ((L->nx - 1) % L->sx || (L->ny - 1) % L->sy) return SDD_EINVAL;
+    if ((L->nx - 1) / L->sx < 2 || (L->ny - 1) / L->sy < 2) return SDD_EINVAL;
+    if ((int64_t)L->nx * L->ny > (int64_t)1 << 31) return SDD_EINVAL;
+    return SDD_OK;
+}
+
+Density to_device(const sdd_density* w)
+{
+    Density D;
+    memset(&D, 0, sizeof(D));
+    D.n_terms = w->n_terms;
+    D.base = w->base;
+    D.fbase = (float)w->base;
+    for (int t = 0; t < w->n_terms; ++t) {
+        const sdd_density_term& T = w->term[t];
+        D.kind[t] = T.kind;
+        D.amp[t] = T.amp;
+        D.coef[t] = T.coef;
+        D.cx[t] = T.cx;
+        D.cy[t] = T.cy;
+        D.r0[t] = T.r0;
+        D.nx[t] = T.nx;
+        D.ny[t] = T.ny;
+        D.famp[t] = (float)T.amp;
+        D.fcoef[t] = (float)T.coef;
+        D.fk2[t] = (float)(-T.coef * 1.4426950408889634073599246810019);
+        D.fcx[t] = (float)T.cx;
+        D.fcy[t] = (float)T.cy;
+        D.fr0[t] = (float)T.r0;
+        D.fnx[t] = (float)T.nx;
+        D.fny[t] = (float)T.ny;
+    }
+    return D;
+}
+
+Bmap to_device(const sdd_bmap* b)
+{
+    Bmap B;
+    B.kind = b->kind;
+    B.n = b->n_per_edge;
+    for (int i = 0; i < 8; ++i) B.p[i] = b->p[i];
+    B.table = b->table;
+    return B;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+sdd_status from_hip(hipError_t e) { return e == hipSuccess ? SDD_OK : SDD_EDEVICE; }
+
+}  // namespace
+
+namespace sdd {
+
+// Paths per work item: about 32 per lane of a wave, balanced over the
+// node's paths, and never so few items that the device idles: with fewer
+// than 8192 items the chunk shrinks (down to one path per lane).
+int64_t walk_chunk(int64_t n_nodes, int64_t paths)
+{
+    const int64_t target = 2048;
+    const int64_t min_items = 8192;
+    int64_t n_chunks = (paths + target - 1) / target;
+    const int64_t want = (min_items + n_nodes - 1) / n_nodes;
+    if (n_chunks < want) n_chunks = want;
+    const int64_t most = (paths + kWave - 1) / kWave;
+    if (n_chunks > most) n_chunks = most;
+    if (n_chunks < 1) n_chunks = 1;
+    return (paths + n_chunks - 1) / n_chunks;
+}
+
+}  // namespace sdd
+
+extern "C" {
+
+const char* sdd_status_string(int status)
+{
+    switch (status) {
+    case SDD_OK: return "ok";
+    case SDD_EINVAL: return "invalid argument";
+    case SDD_ENOSPC: return "workspace too small";
+    case SDD_EDEVICE: return "HIP runtime error";
+    case SDD_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+int32_t sdd_version(void) { return 100; }
+
+sdd_status sdd_create(int32_t device, sdd_ctx** out)
+{
+    if (!out) return SDD_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) return SDD_EDEVICE;
+    if (device < 0 || device >= count) return SDD_EINVAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return SDD_EDEVICE;
+    sdd_ctx* c = new (std::nothrow) sdd_ctx;
+    if (!c) return SDD_EDEVICE;
+    c->device = device;
+    c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return SDD_OK;
+}
+
+void sdd_destroy(sdd_ctx* ctx) { delete ctx; }
+
+size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec)
+{
+    (void)prec;
+    if (n_nodes < 1 || paths_per_node < 1) return 0;
+    const int64_t chunk = walk_chunk(n_nodes, paths_per_node);
+    const int64_t n_chunks = (paths_per_node + chunk - 1) / chunk;
+    size_t b = align_up((size_t)n_nodes * n_chunks * sizeof(Slot), 256);
+    b += align_up((size_t)n_nodes * 2 * sizeof(long long), 256);
+    return b;
+}
+
+sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const double* nodes,
+                                  int64_t n_nodes, int64_t paths_per_node, int64_t path_begin, double dt,
+                                  uint64_t seed, int32_t prec, double t_max, double* mean, double* se, double* sums,
+                                  sdd_walk_stats* stats, sdd_path_record* per_path, void* workspace, size_t ws_bytes,
+                                  void* stream)
+{
+    if (!ctx || !nodes || !mean || !workspace) return SDD_EINVAL;
+    sdd_status s = check_density(w);
+    if (s != SDD_OK) return s;
+    if ((s = check_bmap(bmap)) != SDD_OK) return s;
+    if (n_nodes < 1 || n_nodes > ((int64_t)1 << 32)) return SDD_EINVAL;
+    if (paths_per_node < 1 || path_begin < 0 || path_begin + paths_per_node > ((int64_t)1 << 32)) return SDD_EINVAL;
+    if (!(dt > 0.0) || !(dt < 1.0)) return SDD_EINVAL;
+    if (prec != SDD_FP32 && prec != SDD_FP64) return SDD_EINVAL;
+    if (!(t_max > 0.0)) t_max = 8.0;
+    if (!is_finite(t_max)) return SDD_EINVAL;
+    const double kd = ceil(t_max / dt);
+    if (!(kd >= 1.0) || kd >= 2147483640.0) return SDD_EINVAL;
+    if (ws_bytes < sdd_workspace_bytes(n_nodes, paths_per_node, prec)) return SDD_ENOSPC;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+
+    WalkArgs A;
+    memset(&A, 0, sizeof(A));
+    A.dens = to_device(w);
+    A.bmap = to_device(bmap);
+    A.nodes = nodes;
+    A.n_nodes = n_nodes;
+    A.paths = paths_per_node;
+    A.path_begin = path_begin;
+    A.chunk = walk_chunk(n_nodes, paths_per_node);
+    A.n_chunks = (paths_per_node + A.chunk - 1) / A.chunk;
+    A.n_items = n_nodes * A.n_chunks;
+    A.dt = dt;
+    A.sqrt2dt = sqrt(2.0 * dt);
+    A.kmax = (int32_t)kd;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    char* ws = (char*)workspace;
+    A.slots = (Slot*)ws;
+    long long* node_tot = (long long*)(ws + align_up((size_t)A.n_items * sizeof(Slot), 256));
+    A.per_path = per_path;
+    if (A.n_items / 4 + 1 > 0x7fffffff) return SDD_EINVAL;
+    return from_hip(launch_walk(A, prec, mean, se, sums, stats, node_tot, (hipStream_t)stream));
+}
+
+int64_t sdd_layout_node_count(const sdd_layout* L, int32_t k)
+{
+    if (check_layout(L) != SDD_OK || k < 0) return -1;
+    return (int64_t)(L->sx - 1) * (L->sy - 1) + (int64_t)k * ((int64_t)(L->sx - 1) * L->sy + (int64_t)(L->sy - 1) * L->sx);
+}
+
+sdd_status sdd_layout_nodes(sdd_ctx* ctx, const sdd_layout* L, int32_t k, int32_t placement, const sdd_density* w,
+                            double* nodes, void* stream)
+{
+    if (!ctx || !nodes) return SDD_EINVAL;
+    sdd_status s = check_layout(L);
+    if (s != SDD_OK) return s;
+    if (k < 0 || placement < 0 || placement > 1) return SDD_EINVAL;
+    if (placement == 1 && (s = check_density(w)) != SDD_OK) return s;
+    if (sdd_layout_node_count(L, k) == 0) return SDD_OK;
+    Density D;
+    memset(&D, 0, sizeof(D));
+    if (w) D = to_device(w);
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_layout_nodes(*L, k, placement, D, nodes, (hipStream_t)stream));
+}
+
+sdd_status sdd_bmap_edge1d_table(sdd_ctx* ctx, const sdd_density* w, int32_t n_per_edge, double* table, void* stream)
+{
+    if (!ctx || !table || n_per_edge < 3) return SDD_EINVAL;
+    sdd_status s = check_density(w);
+    if (s != SDD_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_edge1d_table(to_device(w), n_per_edge, table, (hipStream_t)stream));
+}
+
+sdd_status sdd_fill_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t k, const sdd_bmap* bmap,
+                               const double* nodes, const double* values, int32_t interp, double* vert,
+                               double* horiz, void* stream)
+{
+    if (!ctx) return SDD_EINVAL;
+    sdd_status s = check_layout(L);
+    if (s != SDD_OK) return s;
+    if ((s = check_bmap(bmap)) != SDD_OK) return s;
+    if (k < 0 || interp < 0 || interp > 1) return SDD_EINVAL;
+    if (L->sx > 1 && !vert) return SDD_EINVAL;
+    if (L->sy > 1 && !horiz) return SDD_EINVAL;
+    if (sdd_layout_node_count(L, k) > 0 && (!nodes || !values)) return SDD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_fill(*L, k, to_device(bmap), nodes, values, interp, vert, horiz, (hipStream_t)stream));
+}
+
+size_t sdd_subdomain_workspace_bytes(const sdd_layout* L)
+{
+    if (check_layout(L) != SDD_OK) return 0;
+    return subdomain_workspace_bytes(*L);
+}
+
+sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const sdd_layout* L,
+                               const double* vert, const double* horiz, double tol, int32_t max_sweeps,
+                               double* mesh, int32_t* sweeps, double* resid, void* workspace, size_t ws_bytes,
+                               void* stream)
+{
+    if (!ctx || !mesh || !workspace) return SDD_EINVAL;
+    sdd_status s = check_density(w);
+    if (s != SDD_OK) return s;
+    if ((s = check_bmap(bmap)) != SDD_OK) return s;
+    if ((s = check_layout(L)) != SDD_OK) return s;
+    if (L->sx > 1 && !vert) return SDD_EINVAL;
+    if (L->sy > 1 && !horiz) return SDD_EINVAL;
+    if (ws_bytes < subdomain_workspace_bytes(*L)) return SDD_ENOSPC;
+    if (!(tol > 0.0)) tol = 1e-13;
+    if (max_sweeps <= 0) max_sweeps = 100000;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_subdomain_solve(to_device(w), to_device(bmap), *L, vert, horiz, tol, max_sweeps, mesh,
+                                           sweeps, resid, workspace, (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// common.h -- device-side building blocks of the HIP library (gfx950).
+//
+// Density of the linear Winslow generator (eq. (5): w > 0) and the drift
+// grad w / w of its diffusion (eq. (6)/(7b)), the boundary map (Dirichlet
+// data of eq. (5)) and the exit point of a finished Euler-Maruyama step
+// (Sec. 2.2).  Float versions use the CDNA transcendental unit directly
+// (v_exp_f32 is 2^x, v_log_f32 is log2, v_sin/v_cos take turns); double
+// versions use the device math library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sdd.h"
+
+namespace sdd {
+
+constexpr int kWave = 64;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kInvTwoPi = 0.15915494309189535f;
+
+// Density in the layout the kernels read: per-term parameters as arrays so
+// that a wave-uniform term loop indexes kernel arguments (SGPRs).
+struct Density {
+    int32_t n_terms;
+    int32_t kind[SDD_MAX_TERMS];
+    double base;
+    double amp[SDD_MAX_TERMS], coef[SDD_MAX_TERMS], cx[SDD_MAX_TERMS], cy[SDD_MAX_TERMS];
+    double r0[SDD_MAX_TERMS], nx[SDD_MAX_TERMS], ny[SDD_MAX_TERMS];
+    // float copies for the float walk; k2 = -coef * log2(e) so that
+    // exp(-coef t) = 2^(k2 t)
+    float fbase;
+    float famp[SDD_MAX_TERMS], fcoef[SDD_MAX_TERMS], fk2[SDD_MAX_TERMS], fcx[SDD_MAX_TERMS];
+    float fcy[SDD_MAX_TERMS], fr0[SDD_MAX_TERMS], fnx[SDD_MAX_TERMS], fny[SDD_MAX_TERMS];
+};
+
+struct Bmap {
+    int32_t kind;
+    int32_t n;
+    double p[8];
+    const double* table;
+};
+
+// ------------------------------------------------------------------ density
+
+// w and grad w in double (parity mode and the deterministic kernels).
+__device__ inline void density_grad(const Density& D, double xi, double eta, double& w, double& gx, double& gy)
+{
+    double W = D.base, Gx = 0.0, Gy = 0.0;
+    for (int t = 0; t < D.n_terms; ++t) {
+        const double dx = xi - D.cx[t], dy = eta - D.cy[t];
+        const double a = D.amp[t], c = D.coef[t];
+        switch (D.kind[t]) {
+        case SDD_TERM_GAUSS: {
+            const double e = a * exp(-c * (dx * dx + dy * dy));
+            W += e;
+            const double g = -2.0 * c * e;
+            Gx += g * dx;
+            Gy += g * dy;
+        } break;
+        case SDD_TERM_RING: {
+            const double r = sqrt(dx * dx + dy * dy);
+            const double d = r - D.r0[t];
+            const double e = a * exp(-c * d * d);
+            W += e;
+            if (r > 0.0) {
+                const double g = -2.0 * c * d * e / r;
+                Gx += g * dx;
+                Gy += g * dy;
+            }
+        } break;
+        case SDD_TERM_SECH2: {
+            // sech^2 s = 4q/(1+q)^2, tanh s = sign(s)(1-q)/(1+q), q = e^{-2|s|}
+            const double s = c * (D.nx[t] * dx + D.ny[t] * dy);
+            const double q = exp(-2.0 * fabs(s));
+            const double inv = 1.0 / (1.0 + q);
+            const double f = a * 4.0 * q * inv * inv;
+            const double th = copysign((1.0 - q) * inv, s);
+            W += f;
+            const double g = -2.0 * f * th * c;
+            Gx += g * D.nx[t];
+            Gy += g * D.ny[t];
+        } break;
+        case SDD_TERM_SIN2: {
+            const double s = c * (D.nx[t] * dx + D.ny[t] * dy);
+            double sn, cs;
+            sincos(s, &sn, &cs);
+            W += a * sn * sn;
+            const double g = 2.0 * a * sn * cs * c;
+            Gx += g * D.nx[t];
+            Gy += g * D.ny[t];
+        } break;
+        default: break;
+        }
+    }
+    w = W;
+    gx = Gx;
+    gy = Gy;
+}
+
+__device__ inline double density_value(const Density& D, double xi, double eta)
+{
+    double w, gx, gy;
+    density_grad(D, xi, eta, w, gx, gy);
+    return w;
+}
+
+// drift b = grad w / w in float, on the transcendental unit.
+__device__ inline void drift_f32(const Density& D, float xi, float eta, float& bx, float& by)
+{
+    float W = D.fbase, Gx = 0.0f, Gy = 0.0f;
+    for (int t = 0; t < D.n_terms; ++t) {
+        const float dx = xi - D.fcx[t], dy = eta - D.fcy[t];
+        const float a = D.famp[t], c = D.fcoef[t];
+        switch (D.kind[t]) {
+        case SDD_TERM_GAUSS: {
+            const float e = a * __builtin_amdgcn_exp2f(D.fk2[t] * (dx * dx + dy * dy));
+            W += e;
+            const float g = -2.0f * c * e;
+            Gx += g * dx;
+            Gy += g * dy;
+        } break;
+        case SDD_TERM_RING: {
+            const float r2 = dx * dx + dy * dy;
+            const float rinv = __builtin_amdgcn_rsqf(r2);
+            const float r = (r2 > 0.0f) ? r2 * rinv : 0.0f;  // rsq(0) = inf
+            const float d = r - D.fr0[t];
+            const float e = a * __builtin_amdgcn_exp2f(D.fk2[t] * d * d);
+            W += e;
+            const float g = (r2 > 0.0f) ? (-2.0f * c * d * e * rinv) : 0.0f;
+            Gx += g * dx;
+            Gy += g * dy;
+        } break;
+        case SDD_TERM_SECH2: {
+            const float s = c * (D.fnx[t] * dx + D.fny[t] * dy);
+            const float q = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(s));
+            const float inv = __builtin_amdgcn_rcpf(1.0f + q);
+            const float f = a * 4.0f * q * inv * inv;
+            const float th = copysignf((1.0f - q) * inv, s);
+            W += f;
+            const float g = -2.0f * f * th * c;
+            Gx += g * D.fnx[t];
+            Gy += g * D.fny[t];
+        } break;
+        case SDD_TERM_SIN2: {
+            const float s = c * (D.fnx[t] * dx + D.fny[t] * dy);
+            float turns = s * kInvTwoPi;
+            turns = turns - floorf(turns);
+            const float sn = __builtin_amdgcn_sinf(turns);
+            const float cs = __builtin_amdgcn_cosf(turns);
+            W += a * sn * sn;
+            const float g = 2.0f * a * sn * cs * c;
+            Gx += g * D.fnx[t];
+            Gy += g * D.fny[t];
+        } break;
+        default: break;
+        }
+    }
+    const float iw = __builtin_amdgcn_rcpf(W);
+    bx = Gx * iw;
+    by = Gy * iw;
+}
+
+__device__ inline void drift_f64(const Density& D, double xi, double eta, double& bx, double& by)
+{
+    double w, gx, gy;
+    density_grad(D, xi, eta, w, gx, gy);
+    bx = gx / w;
+    by = gy / w;
+}
+
+// ------------------------------------------------------------ boundary map
+
+// (x_b, y_b) at boundary point (xi, eta) of side `side` (0: xi=0, 1: xi=1,
+// 2: eta=0, 3: eta=1).
+__device__ inline void bmap_eval(const Bmap& B, int side, double xi, double eta, double& x, double& y)
+{
+    switch (B.kind) {
+    case SDD_BMAP_AFFINE:
+        x = B.p[0] + B.p[1] * xi + B.p[2] * eta;
+        y = B.p[3] + B.p[4] * xi + B.p[5] * eta;
+        return;
+    case SDD_BMAP_ANNULUS: {
+        const double rho = B.p[0] + (B.p[1] - B.p[0]) * xi;
+        const double th = B.p[2] + (B.p[3] - B.p[2]) * eta;
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        x = rho * cs;
+        y = rho * sn;
+        return;
+    }
+    case SDD_BMAP_TABLE: {
+        const double s = (side < 2) ? eta : xi;
+        const double pos = s * (double)(B.n - 1);
+        int q = (int)floor(pos);
+        q = q < 0 ? 0 : (q > B.n - 2 ? B.n - 2 : q);
+        const double f = pos - (double)q;
+        const double* v = B.table + ((size_t)side * B.n + q) * 2;
+        x = v[0] + f * (v[2] - v[0]);
+        y = v[1] + f * (v[3] - v[1]);
+        return;
+    }
+    default:
+        x = xi;
+        y = eta;
+        return;
+    }
+}
+
+// Boundary side of a point known to lie on the boundary, first match in the
+// order xi=0, xi=1, eta=0, eta=1.
+__device__ inline int boundary_side(double xi, double eta)
+{
+    if (xi == 0.0) return 0;
+    if (xi == 1.0) return 1;
+    if (eta == 0.0) return 2;
+    return 3;
+}
+
+// ------------------------------------------------------------ exit point
+
+// First crossing of segment P -> Q with the square boundary (P inside, Q on
+// or outside), in double.  Ties keep the earlier side of xi=0, xi=1, eta=0,
+// eta=1.  E gets the side's coordinate exactly, the other one clamped.
+__device__ inline int exit_point(double px, double py, double qx, double qy, double& ex, double& ey)
+{
+    double tb = 2.0;
+    int side = 0;
+    if (qx <= 0.0) { const double t = (0.0 - px) / (qx - px); if (t < tb) { tb = t; side = 0; } }
+    if (qx >= 1.0) { const double t = (1.0 - px) / (qx - px); if (t < tb) { tb = t; side = 1; } }
+    if (qy <= 0.0) { const double t = (0.0 - py) / (qy - py); if (t < tb) { tb = t; side = 2; } }
+    if (qy >= 1.0) { const double t = (1.0 - py) / (qy - py); if (t < tb) { tb = t; side = 3; } }
+    double x = px + tb * (qx - px);
+    double y = py + tb * (qy - py);
+    x = fmin(fmax(x, 0.0), 1.0);
+    y = fmin(fmax(y, 0.0), 1.0);
+    if (side == 0) x = 0.0;
+    if (side == 1) x = 1.0;
+    if (side == 2) y = 0.0;
+    if (side == 3) y = 1.0;
+    ex = x;
+    ey = y;
+    return side;
+}
+
+// Nearest boundary point of an interior point (step-capped paths); ties in
+// the same side order.
+__device__ inline int nearest_side(double px, double py, double& ex, double& ey)
+{
+    int side = 0;
+    double best = px;
+    if (1.0 - px < best) { best = 1.0 - px; side = 1; }
+    if (py < best) { best = py; side = 2; }
+    if (1.0 - py < best) { side = 3; }
+    ex = (side == 0) ? 0.0 : (side == 1 ? 1.0 : px);
+    ey = (side == 2) ? 0.0 : (side == 3 ? 1.0 : py);
+    return side;
+}
+
+// Neumaier compensated accumulation.
+__device__ inline void nadd(double& s, double& c, double v)
+{
+    const double t = s + v;
+    c += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
+    s = t;
+}
+
+}  // namespace sdd

@@ -1,0 +1,65 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/sdd.h declares (no compute: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("sdd_interface_estimate", "sdd_subdomain_solve", "sdd_create", "sdd_workspace_bytes",
+                 "sdd_fill_interfaces", "sdd_layout_nodes", "sdd_bmap_edge1d_table"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1310_3435_amd as sdd
+    if not os.path.exists(sdd.LIB_PATH):
+        pytest.fail("libsdd.so is not built: run __graft_entry__.build()")
+    L = ctypes.CDLL(sdd.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(sdd.EXPORTS) == set(declared_functions())
+
+
+def test_host_only_entry_points_work_without_a_gpu():
+    import paper_1310_3435_amd as sdd
+    L = sdd.lib()
+    assert sdd.sdd_version() >= 100
+    assert L.sdd_status_string(-1) == b"invalid argument"
+    assert sdd.sdd_layout_node_count({"nx": 257, "ny": 257, "sx": 4, "sy": 4}, 63) == 1521
+    assert sdd.sdd_layout_node_count({"nx": 1025, "ny": 1025, "sx": 8, "sy": 8}, 32) == 3633
+    assert sdd.sdd_layout_node_count({"nx": 65, "ny": 33, "sx": 2, "sy": 1}, 15) == 15
+    with pytest.raises(sdd.SddError):
+        sdd.sdd_layout_node_count({"nx": 64, "ny": 33, "sx": 2, "sy": 1}, 15)
+    assert sdd.sdd_workspace_bytes(1521, 10000) > 0
+    assert sdd.sdd_workspace_bytes(0, 10000) == 0
+    assert sdd.sdd_subdomain_workspace_bytes({"nx": 65, "ny": 33, "sx": 2, "sy": 1}) > 65 * 33 * 16
+
+
+def test_struct_layouts_match_the_header():
+    import paper_1310_3435_amd as sdd
+    assert ctypes.sizeof(sdd.sdd_density_term) == 64
+    assert ctypes.sizeof(sdd.sdd_density) == 16 + 4 * 64
+    assert ctypes.sizeof(sdd.sdd_bmap) == 8 + 64 + 8
+    assert ctypes.sizeof(sdd.sdd_layout) == 16
+    assert sdd.PATH_RECORD.itemsize == 32
+
+
+def test_product_path_does_not_import_the_oracle():
+    src = open(os.path.join(ROOT, "paper_1310_3435_amd", "__init__.py")).read()
+    assert "import oracle" not in src and "from oracle" not in src
+    for f in os.listdir(os.path.join(ROOT, "paper_1310_3435_amd", "csrc")):
+        s = open(os.path.join(ROOT, "paper_1310_3435_amd", "csrc", f)).read()
+        assert "sddref" not in s and "oracle" not in s.lower()

@@ -1,0 +1,159 @@
+"""GPU parity of the deterministic mesh kernels (placement, edge data,
+interface fill, batched subdomain solves) and of the whole pipeline,
+against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1310_3435_amd as sdd
+    return sdd.Context(0)
+
+
+LAYOUTS = [
+    ({"nx": 65, "ny": 33, "sx": 2, "sy": 1}, 15),
+    ({"nx": 257, "ny": 257, "sx": 4, "sy": 4}, 63),
+    ({"nx": 129, "ny": 97, "sx": 8, "sy": 3}, 5),
+    ({"nx": 1025, "ny": 1025, "sx": 8, "sy": 8}, 32),
+]
+
+
+@pytest.mark.parametrize("placement", ["uniform", "equidistributed"])
+@pytest.mark.parametrize("L,k", LAYOUTS, ids=["1x2", "4x4", "8x3", "8x8"])
+def test_layout_nodes(ctx, ref, L, k, placement):
+    import paper_1310_3435_amd as sdd
+    d = W.cfg_annulus_fp32()["density"]
+    say(f"layout_nodes {L} k={k} {placement}")
+    g = sdd.sdd_layout_nodes(ctx, L, k, placement, d).cpu().numpy()
+    r = ref.layout_nodes(L, k, placement, d)
+    assert g.shape == r.shape
+    if placement == "uniform":
+        assert np.array_equal(g, r)
+    else:
+        assert np.max(np.abs(g - r)) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [3, 257, 4097, 16385])
+def test_edge1d_table(ctx, ref, n):
+    import paper_1310_3435_amd as sdd
+    for d in (W.cfg_sin2_sweep()["density"], W.random_density(8)):
+        say(f"edge1d table n={n}")
+        g = sdd.sdd_bmap_edge1d_table(ctx, d, n).cpu().numpy()
+        r = ref.edge1d_table(d, n)
+        assert np.max(np.abs(g - r)) <= 1e-14
+
+
+@pytest.mark.parametrize("interp", ["linear", "pchip"])
+@pytest.mark.parametrize("L,k", LAYOUTS[:3], ids=["1x2", "4x4", "8x3"])
+def test_fill_interfaces(ctx, ref, L, k, interp):
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    d = W.cfg_annulus_fp32()["density"]
+    bm = {"kind": "annulus", "p": [1.0, 2.0, 0.0, 0.5 * math.pi]}
+    nodes = ref.layout_nodes(L, k, "equidistributed", d)
+    rng = np.random.default_rng(k)
+    vals = rng.normal(size=nodes.shape)
+    vals[::7] = vals[::7] * 0 + 0.25          # flat runs exercise the zero-slope branch
+    say(f"fill {L} k={k} {interp}")
+    gv, gh = sdd.sdd_fill_interfaces(ctx, L, k, bm, torch.as_tensor(nodes).cuda(), torch.as_tensor(vals).cuda(),
+                                     interp)
+    rv, rh = ref.fill_interfaces(L, k, bm, nodes, vals, interp)
+    assert np.max(np.abs(gv.cpu().numpy() - rv), initial=0) <= 1e-13
+    assert np.max(np.abs(gh.cpu().numpy() - rh), initial=0) <= 1e-13
+
+
+@pytest.mark.parametrize("L", [
+    {"nx": 65, "ny": 33, "sx": 2, "sy": 1},
+    {"nx": 129, "ny": 129, "sx": 4, "sy": 4},
+    {"nx": 41, "ny": 61, "sx": 4, "sy": 3},
+    {"nx": 257, "ny": 257, "sx": 2, "sy": 2},
+    {"nx": 513, "ny": 257, "sx": 2, "sy": 1},
+], ids=["33sq", "33sq_4x4", "aniso", "129sq", "257sq"])
+def test_subdomain_solve_matches_direct_solve(ctx, ref, L):
+    """SOR to its stopping tolerance against the oracle's exact LU solution;
+    the error bound is the last update size over (1 - SOR radius)."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    d = W.random_density(4)
+    bm = {"kind": "annulus", "p": [1.0, 2.0, 0.0, 0.5 * math.pi]}
+    nx, ny, sx, sy = L["nx"], L["ny"], L["sx"], L["sy"]
+    mx, my = (nx - 1) // sx, (ny - 1) // sy
+    B = ref.Bmap(bm)
+    frame = ref.boundary_frame(B, nx, ny)
+    rng = np.random.default_rng(nx + ny)
+    # interface values: a smooth field plus noise (the MC error)
+    xi, eta = np.meshgrid(np.arange(nx) / (nx - 1), np.arange(ny) / (ny - 1))
+    base = np.stack([1 + xi, 0.5 * math.pi * eta], -1)
+    field = np.stack([base[..., 0] * np.cos(base[..., 1]), base[..., 0] * np.sin(base[..., 1])], -1)
+    vert = np.stack([field[:, a * mx] for a in range(1, sx)]) if sx > 1 else np.zeros((0, ny, 2))
+    horiz = np.stack([field[b * my, :] for b in range(1, sy)]) if sy > 1 else np.zeros((0, nx, 2))
+    vert[:, 1:-1] += rng.normal(scale=1e-3, size=vert[:, 1:-1].shape)
+    horiz[:, 1:-1] += rng.normal(scale=1e-3, size=horiz[:, 1:-1].shape)
+    for b in range(1, sy):
+        for a in range(1, sx):
+            horiz[b - 1, a * mx] = vert[a - 1, b * my]
+    vert[:, 0] = frame[0, [a * mx for a in range(1, sx)]] if sx > 1 else vert[:, 0]
+    vert[:, -1] = frame[-1, [a * mx for a in range(1, sx)]] if sx > 1 else vert[:, -1]
+    if sy > 1:
+        horiz[:, 0] = frame[[b * my for b in range(1, sy)], 0]
+        horiz[:, -1] = frame[[b * my for b in range(1, sy)], -1]
+    say(f"subdomain_solve {L}")
+    tv = torch.as_tensor(vert).cuda() if sx > 1 else None
+    th = torch.as_tensor(horiz).cuda() if sy > 1 else None
+    sol = sdd.sdd_subdomain_solve(ctx, d, bm, L, tv, th, tol=1e-14)
+    mesh = sol["mesh"].cpu().numpy()
+    sweeps = sol["sweeps"].cpu().numpy()
+    resid = sol["resid"].cpu().numpy()
+    say(f"sweeps {sweeps.min()}..{sweeps.max()}, last change {resid.max():.2e}")
+    r = ref.subdomain_solve(d, B, L, vert, horiz)
+    err = np.max(np.abs(mesh - r))
+    say(f"max |GPU - direct| = {err:.3e}")
+    assert np.all(resid <= 1e-14)
+    assert err <= 1e-10
+    # boundary values: device and host sin/cos may differ by an ulp
+    assert np.max(np.abs(mesh[0] - r[0])) <= 4e-16 and np.max(np.abs(mesh[:, 0] - r[:, 0])) <= 4e-16
+
+
+def test_pipeline_plain_fp64_matches_oracle(ctx, ref):
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    c = W.cfg_plain_fp64()
+    say("pipeline plain_fp64_gauss")
+    out = sdd.run_pipeline(ctx, c)
+    torch.cuda.synchronize()
+    r = ref.pipeline(c)
+    mesh = out["mesh"].cpu().numpy()
+    assert np.array_equal(out["nodes"].cpu().numpy(), r["nodes"])
+    assert np.max(np.abs(out["est"]["mean"].cpu().numpy() - r["est"]["mean"])) <= 1e-10
+    err = np.max(np.abs(mesh - r["mesh"]))
+    say(f"pipeline max |GPU - oracle| = {err:.3e}")
+    assert err <= 1e-9
+
+
+def test_pipeline_annulus_small_matches_oracle(ctx, ref):
+    """The curved workload's kinds (equidistributed points, monotone cubic
+    fill, annulus map, shear-layer density) on a reduced layout."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    c = W.cfg_annulus_fp32()
+    c.update(layout={"nx": 129, "ny": 129, "sx": 8, "sy": 8}, k=6, paths=256, dt=1e-4, prec="fp64")
+    say("pipeline annulus reduced, fp64")
+    out = sdd.run_pipeline(ctx, c)
+    torch.cuda.synchronize()
+    r = ref.pipeline(c)
+    assert np.max(np.abs(out["nodes"].cpu().numpy() - r["nodes"])) <= 1e-13
+    err = np.max(np.abs(out["mesh"].cpu().numpy() - r["mesh"]))
+    say(f"pipeline annulus max |GPU - oracle| = {err:.3e}")
+    assert err <= 1e-9

@@ -1,0 +1,171 @@
+"""GPU parity of the interface walk against the CPU oracle (same Philox
+counters, so individual paths are compared).
+
+Bars:
+* double precision: per-path exit points within 1e-12, equal exit steps
+  except roundoff flips (counted; expected ~0), node means and standard
+  errors within 1e-10 on flip-free nodes;
+* float stepping: per-path agreement with the oracle's float walk except
+  rare flips, and node estimates within 3 standard errors of the
+  double-precision oracle (they share the uniforms, so the difference
+  isolates precision effects).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import compare_paths, gpu_estimate, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1310_3435_amd as sdd
+    return sdd.Context(0)
+
+
+def _flip_free_nodes(flips):
+    return ~flips.any(axis=1)
+
+
+def test_fp64_paths_match_oracle_on_the_small_workload(ctx, ref):
+    c = W.cfg_plain_fp64()
+    nodes = ref.layout_nodes(c["layout"], c["k"])
+    g = gpu_estimate(ctx, c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], "fp64", per_path=True)
+    r = ref.interface_estimate(c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], per_path=True)
+    flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+    say(f"fp64 flips {int(flips.sum())} of {flips.size}, max exit diff {dmax:.3e}")
+    assert flips.sum() <= max(1, flips.size // 10000)
+    assert dmax <= 1e-12
+    ok = _flip_free_nodes(flips)
+    assert ok.sum() >= len(ok) - 1
+    assert np.max(np.abs(g["mean"][ok] - r["mean"][ok])) <= 1e-10
+    assert np.max(np.abs(g["se"][ok] - r["se"][ok])) <= 1e-10
+    assert np.array_equal(g["per_path"]["side"][~flips], r["per_path"]["side"][~flips])
+    assert abs(g["steps"] - r["steps"]) <= int(flips.sum()) * 2 * 10**5
+    assert g["paths"] == r["paths"] and g["capped"] == r["capped"] == 0
+
+
+@pytest.mark.parametrize("bm", [
+    {"kind": "identity"},
+    {"kind": "affine", "p": [0.3, 2.0, -0.5, -1.0, 0.25, 3.0]},
+    {"kind": "annulus", "p": [1.0, 2.0, 0.0, 0.5 * math.pi]},
+    {"kind": "edge1d", "n_per_edge": 1025},
+], ids=["identity", "affine", "annulus", "edge1d"])
+@pytest.mark.parametrize("dseed", [3, 6])
+def test_fp64_paths_match_oracle_all_terms_and_maps(ctx, ref, bm, dseed):
+    d = W.random_density(dseed, 4)
+    nodes = W.random_nodes(24, dseed + 100)
+    g = gpu_estimate(ctx, d, bm, nodes, 300, 1e-3, 1000 + dseed, "fp64", per_path=True)
+    r = ref.interface_estimate(d, bm, nodes, 300, 1e-3, 1000 + dseed, per_path=True)
+    flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+    say(f"{bm['kind']} d{dseed}: flips {int(flips.sum())}, max exit diff {dmax:.3e}")
+    assert flips.sum() <= 1
+    assert dmax <= 1e-12
+    ok = _flip_free_nodes(flips)
+    assert np.max(np.abs(g["mean"][ok] - r["mean"][ok])) <= 1e-10
+    assert np.max(np.abs(g["se"][ok] - r["se"][ok])) <= 1e-10
+
+
+def test_fp32_walk_matches_oracle_float_walk_and_double_estimates(ctx, ref):
+    c = W.cfg_plain_fp64()
+    nodes = ref.layout_nodes(c["layout"], c["k"])
+    g = gpu_estimate(ctx, c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], "fp32", per_path=True)
+    r32 = ref.interface_estimate(c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], "fp32",
+                                 per_path=True)
+    r64 = ref.interface_estimate(c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], "fp64")
+    flips, dmax = compare_paths(g["per_path"], r32["per_path"], 1e-5)
+    say(f"fp32 vs oracle fp32: flips {int(flips.sum())} of {flips.size}, max exit diff {dmax:.3e}")
+    assert flips.mean() < 2e-3
+    assert dmax < 1e-4
+    # spec criterion: within 3 standard errors of the double oracle
+    z64 = np.abs(g["mean"] - r64["mean"]) / r64["se"]
+    say(f"fp32 vs fp64 oracle: max |diff|/SE = {z64.max():.3f}, max |diff| = {np.abs(g['mean'] - r64['mean']).max():.3e}")
+    assert np.all(z64 <= 3.0)
+    assert np.all(np.abs(g["mean"] - r32["mean"]) <= 0.5 * r32["se"])
+
+
+def test_full_size_ring_workload_sampled_nodes(ctx, ref):
+    """The throughput workload at full size (1521 nodes x 1e4 paths, dt=1e-5,
+    float walk) in the benchmark's launch configuration; sampled nodes
+    against the double-precision oracle, every node against symmetry."""
+    c = W.cfg_ring_fp32()
+    nodes = ref.layout_nodes(c["layout"], c["k"])
+    g = gpu_estimate(ctx, c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], "fp32")
+    n = nodes.shape[0]
+    assert np.all(np.isfinite(g["mean"])) and np.all((g["mean"] > 0) & (g["mean"] < 1))
+    assert g["paths"] == n * c["paths"] and g["capped"] == 0
+    sample = np.array([0, 5, 400, 800, 1100, 1520])
+    say(f"oracle fp64 on {len(sample)} sampled nodes")
+    r = ref.interface_estimate(c["density"], c["bmap"], nodes[sample], c["paths"], c["dt"], c["seed"],
+                               node_ids=sample)
+    z = np.abs(g["mean"][sample] - r["mean"]) / r["se"]
+    say(f"ring fp32 vs fp64 oracle sampled: max z {z.max():.3f}, max |diff| {np.abs(g['mean'][sample] - r['mean']).max():.3e}")
+    assert np.all(z <= 3.0)
+    # mirror symmetry of the ring about xi = 1/2: x(1-xi, eta) = 1 - x(xi, eta)
+    key = {tuple(np.rint(p * 256).astype(int)): i for i, p in enumerate(nodes)}
+    zs = []
+    for i, p in enumerate(nodes):
+        j = key[(256 - int(round(p[0] * 256)), int(round(p[1] * 256)))]
+        if j > i:
+            s = math.hypot(g["se"][i, 0], g["se"][j, 0])
+            zs.append((g["mean"][i, 0] + g["mean"][j, 0] - 1.0) / s)
+    zs = np.array(zs)
+    say(f"mirror pairs {len(zs)}: max |z| {np.abs(zs).max():.2f}, mean z^2 {np.mean(zs**2):.3f}")
+    assert np.abs(zs).max() < 5.5
+    assert np.mean(zs**2) < 1.3
+
+
+def test_edge_cases(ctx, ref):
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    d = W.random_density(11, 3)
+    bm = {"kind": "identity"}
+    # one path: SE is 0, the mean is that path's value
+    nodes = W.random_nodes(3, 5)
+    g = gpu_estimate(ctx, d, bm, nodes, 1, 1e-3, 9, "fp64", per_path=True)
+    r = ref.interface_estimate(d, bm, nodes, 1, 1e-3, 9, per_path=True)
+    assert np.all(g["se"] == 0)
+    assert np.max(np.abs(g["mean"] - r["mean"])) <= 1e-12
+    # ragged: paths not a multiple of the wave, a single node
+    for N in (63, 65, 130, 4097):
+        g = gpu_estimate(ctx, d, bm, nodes[:1], N, 1e-3, 10, "fp64", per_path=True)
+        r = ref.interface_estimate(d, bm, nodes[:1], N, 1e-3, 10, per_path=True)
+        flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+        assert flips.sum() == 0 and dmax <= 1e-12
+        assert abs(g["mean"] - r["mean"]).max() <= 1e-10
+    # path ranges: counters follow the path index
+    g = gpu_estimate(ctx, d, bm, nodes, 100, 1e-3, 12, "fp64", per_path=True, path_begin=1000)
+    r = ref.interface_estimate(d, bm, nodes, 100, 1e-3, 12, path_begin=1000, per_path=True)
+    flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+    assert flips.sum() == 0 and dmax <= 1e-12
+    # step cap: tiny t_max caps most paths, identically on both sides
+    g = gpu_estimate(ctx, d, bm, nodes, 200, 1e-3, 13, "fp64", per_path=True, t_max=4.5e-3)
+    r = ref.interface_estimate(d, bm, nodes, 200, 1e-3, 13, t_max=4.5e-3, per_path=True)
+    assert g["capped"] == r["capped"] > 0
+    assert np.array_equal(g["per_path"]["capped"], r["per_path"]["capped"])
+    flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+    assert flips.sum() == 0 and dmax <= 1e-12
+    # a node on the boundary gives NaN, the others are unaffected
+    bad = np.array([[0.5, 0.5], [0.0, 0.3], [0.25, 0.75]])
+    g = gpu_estimate(ctx, d, bm, bad, 64, 1e-3, 14, "fp64")
+    assert np.all(np.isnan(g["mean"][1])) and np.all(np.isfinite(g["mean"][[0, 2]]))
+    r = ref.interface_estimate(d, bm, bad[[0, 2]], 64, 1e-3, 14, node_ids=[0, 2])
+    assert np.max(np.abs(g["mean"][[0, 2]] - r["mean"])) <= 1e-10
+    # determinism: two runs are bitwise equal
+    a = gpu_estimate(ctx, d, bm, nodes, 5000, 1e-3, 15, "fp32")
+    b = gpu_estimate(ctx, d, bm, nodes, 5000, 1e-3, 15, "fp32")
+    assert np.array_equal(a["mean"], b["mean"]) and np.array_equal(a["sums"], b["sums"])
+    # invalid arguments are rejected before any launch
+    t = torch.as_tensor(nodes).cuda()
+    for kw in ({"dt": 0.0}, {"dt": 1.5}, {"prec": "bf16"}):
+        args = dict(dt=1e-3, prec="fp64")
+        args.update(kw)
+        with pytest.raises((sdd.SddError, KeyError)):
+            sdd.sdd_interface_estimate(ctx, d, bm, t, 10, args["dt"], 1, args["prec"])
+    with pytest.raises(sdd.SddError):
+        sdd.sdd_interface_estimate(ctx, {"base": -1.0, "terms": []}, bm, t, 10, 1e-3, 1)
