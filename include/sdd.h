@@ -141,7 +141,7 @@ void sdd_destroy(sdd_ctx* ctx);
  * Sec. 2.2): Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
  * (m, p, g, 0) for step pair m of path p of node g (g = index in `nodes`);
  * steps 2m and 2m+1 take words (0,1) and (2,3).  Uniforms
- * u = ((r >> 9) + 1/2) 2^-23; normals by Box-Muller,
+ * u = ((r mod 2^23) + 1/2) 2^-23; normals by Box-Muller,
  * sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).  Path p is therefore the
  * same wherever and whenever it is walked.
  *
@@ -150,9 +150,13 @@ void sdd_destroy(sdd_ctx* ctx);
  * first step that ends on or outside the square; its exit point is the
  * first crossing of that step's segment with the boundary, computed in
  * double in both modes, and its value is the boundary map there.  A path
- * still inside after ceil(t_max/dt) steps is capped: it takes the value at
- * the nearest boundary point and is counted in stats->capped.  Per-node
- * sums are accumulated in double with compensation.
+ * still inside after ceil(t_max/dt) steps, rounded up to an even count, is
+ * capped: it takes the value at the nearest boundary point and is counted
+ * in stats->capped.  Per-node sums are accumulated in double with
+ * compensation, in a fixed order, so results do not depend on scheduling.
+ * The workspace holds every path's last step (16 bytes in float, 32 in
+ * double) and step count (4 bytes): n_nodes * N must stay below
+ * 2^32 - 2^24.
  *
  *   w, bmap      host structs (bmap->table, if any, is device memory)
  *   nodes        device [n_nodes][2], every point strictly inside (0,1)^2
@@ -166,9 +170,9 @@ void sdd_destroy(sdd_ctx* ctx);
  *   stats        device sdd_walk_stats or NULL (overwritten)
  *   per_path     device [n][N] sdd_path_record or NULL
  *   workspace    device, >= sdd_workspace_bytes(n_nodes, N, prec) bytes
- * Errors: SDD_EINVAL (bad argument; node positions are checked on the
- * device side only by the walk itself, which treats a node on or outside the
- * boundary as exiting at once), SDD_ENOSPC, SDD_EDEVICE. */
+ * Errors: SDD_EINVAL (bad argument), SDD_ENOSPC, SDD_EDEVICE.  Node
+ * positions live on the device and are not read by the host: a node on or
+ * outside the boundary walks no path and gets NaN mean, SE and sums. */
 size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec);
 
 sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap,
@@ -223,8 +227,9 @@ sdd_status sdd_fill_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t k, con
  * 5-point stencil (Sec. 3.2 uses centred differences), w at the edge
  * midpoints, x_P = sum a_nb x_nb / sum a_nb with a_E = w(xi+h/2, eta)/h^2
  * etc.  Solved by red-black successive over-relaxation until the largest
- * change of a sweep is <= tol (tol <= 0 selects 1e-13) or max_sweeps
- * (<= 0 selects 100000) sweeps.
+ * change of a sweep is <= tol (tol <= 0 selects 1e-13), until that change
+ * stops falling (no halving within 512 sweeps: the rounding floor), or
+ * after max_sweeps (<= 0 selects 100000) sweeps.
  * mesh: device [ny][nx][2]; on return the boundary ring holds the map, the
  * interface lines hold vert/horiz, every subdomain interior its solution.
  * sweeps (device [sx*sy] int32 or NULL) and resid (device [sx*sy] double or

@@ -24,13 +24,14 @@
  *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
  *     counter = (step pair m, path p, node g, 0); step 2m uses words 0,1 and
  *     step 2m+1 uses words 2,3;
- *   - uniforms u = ((r >> 9) + 1/2) * 2^-23, exactly representable in both
- *     float and double; normals by Box-Muller,
+ *   - uniforms u = ((r mod 2^23) + 1/2) * 2^-23 (the low 23 bits of a word),
+ *     exactly representable in both float and double; normals by Box-Muller,
  *     (z_xi, z_eta) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b);
  *   - exit point: first crossing of the last step's segment with the square
  *     boundary, in double precision; ties go to xi=0, xi=1, eta=0, eta=1;
- *   - step cap ceil(t_max / dt); a capped path takes the boundary value at
- *     the nearest boundary point and is counted.
+ *   - step cap ceil(t_max / dt) rounded up to an even count (a Philox block
+ *     serves two steps); a capped path takes the boundary value at the
+ *     nearest boundary point and is counted.
  */
 #include <math.h>
 #include <stdint.h>
@@ -82,7 +83,7 @@ void sddref_philox_many(int64_t n, const uint32_t* ctr, const uint32_t key[2], u
 
 /* ---------------------------------------------------------------- normals */
 
-static double uniform23(uint32_t r) { return ((double)(r >> 9) + 0.5) * 0x1p-23; }
+static double uniform23(uint32_t r) { return ((double)(r & 0x7FFFFFu) + 0.5) * 0x1p-23; }
 
 static void box_muller64(uint32_t ra, uint32_t rb, double* z0, double* z1)
 {
@@ -97,8 +98,8 @@ static void box_muller64(uint32_t ra, uint32_t rb, double* z0, double* z1)
 static void box_muller32(uint32_t ra, uint32_t rb, float* z0, float* z1)
 {
     const float two_pi = 6.28318530717958647692f;
-    float ua = ((float)(ra >> 9) + 0.5f) * 0x1p-23f;
-    float ub = ((float)(rb >> 9) + 0.5f) * 0x1p-23f;
+    float ua = ((float)(ra & 0x7FFFFFu) + 0.5f) * 0x1p-23f;
+    float ub = ((float)(rb & 0x7FFFFFu) + 0.5f) * 0x1p-23f;
     float radius = sqrtf(-2.0f * logf(ua));
     float angle = two_pi * ub;
     *z0 = radius * cosf(angle);
@@ -447,7 +448,8 @@ int sddref_interface_estimate(const ref_density* d, const ref_bmap* b, const dou
         if (!(a > 0.0 && a < 1.0 && c > 0.0 && c < 1.0)) return -1;
     }
     if (!(t_max > 0.0)) t_max = 8.0;
-    const int64_t kmax = (int64_t)ceil(t_max / dt);
+    int64_t kmax = (int64_t)ceil(t_max / dt);
+    kmax += kmax & 1;
     const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     int64_t tot_steps = 0, tot_capped = 0;
 #ifdef _OPENMP

@@ -78,6 +78,8 @@ Density to_device(const sdd_density* w)
         D.famp[t] = (float)T.amp;
         D.fcoef[t] = (float)T.coef;
         D.fk2[t] = (float)(-T.coef * 1.4426950408889634073599246810019);
+        D.fla[t] = (float)log2(T.amp);  // -inf for a zero amplitude: the term vanishes
+        D.fm2c[t] = (float)(-2.0 * T.coef);
         D.fcx[t] = (float)T.cx;
         D.fcy[t] = (float)T.cy;
         D.fr0[t] = (float)T.r0;
@@ -101,24 +103,24 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 sdd_status from_hip(hipError_t e) { return e == hipSuccess ? SDD_OK : SDD_EDEVICE; }
 
+// tickets (node, path) are 32-bit; keep clear of the top for the batch fetches
+constexpr int64_t kMaxTickets = ((int64_t)1 << 32) - ((int64_t)1 << 24);
+
 }  // namespace
 
 namespace sdd {
 
-// Paths per work item: about 32 per lane of a wave, balanced over the
-// node's paths, and never so few items that the device idles: with fewer
-// than 8192 items the chunk shrinks (down to one path per lane).
-int64_t walk_chunk(int64_t n_nodes, int64_t paths)
+WalkWorkspace walk_workspace(int64_t n_nodes, int64_t paths, int prec)
 {
-    const int64_t target = 2048;
-    const int64_t min_items = 8192;
-    int64_t n_chunks = (paths + target - 1) / target;
-    const int64_t want = (min_items + n_nodes - 1) / n_nodes;
-    if (n_chunks < want) n_chunks = want;
-    const int64_t most = (paths + kWave - 1) / kWave;
-    if (n_chunks > most) n_chunks = most;
-    if (n_chunks < 1) n_chunks = 1;
-    return (paths + n_chunks - 1) / n_chunks;
+    WalkWorkspace W;
+    const size_t total = (size_t)n_nodes * (size_t)paths;
+    const size_t real = (prec == SDD_FP32) ? sizeof(float) : sizeof(double);
+    W.pq_off = 0;
+    W.info_off = align_up(W.pq_off + total * 4 * real, 256);
+    W.counter_off = align_up(W.info_off + total * sizeof(uint32_t), 256);
+    W.node_tot_off = align_up(W.counter_off + sizeof(unsigned long long), 256);
+    W.bytes = align_up(W.node_tot_off + (size_t)n_nodes * 2 * sizeof(long long), 256);
+    return W;
 }
 
 }  // namespace sdd
@@ -160,13 +162,9 @@ void sdd_destroy(sdd_ctx* ctx) { delete ctx; }
 
 size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec)
 {
-    (void)prec;
     if (n_nodes < 1 || paths_per_node < 1) return 0;
-    const int64_t chunk = walk_chunk(n_nodes, paths_per_node);
-    const int64_t n_chunks = (paths_per_node + chunk - 1) / chunk;
-    size_t b = align_up((size_t)n_nodes * n_chunks * sizeof(Slot), 256);
-    b += align_up((size_t)n_nodes * 2 * sizeof(long long), 256);
-    return b;
+    if (n_nodes * paths_per_node >= kMaxTickets) return 0;
+    return walk_workspace(n_nodes, paths_per_node, prec).bytes;
 }
 
 sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const double* nodes,
@@ -179,15 +177,18 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
     sdd_status s = check_density(w);
     if (s != SDD_OK) return s;
     if ((s = check_bmap(bmap)) != SDD_OK) return s;
-    if (n_nodes < 1 || n_nodes > ((int64_t)1 << 32)) return SDD_EINVAL;
-    if (paths_per_node < 1 || path_begin < 0 || path_begin + paths_per_node > ((int64_t)1 << 32)) return SDD_EINVAL;
+    if (n_nodes < 1 || paths_per_node < 1 || path_begin < 0) return SDD_EINVAL;
+    if (n_nodes * paths_per_node >= kMaxTickets) return SDD_EINVAL;
+    if (path_begin + paths_per_node > ((int64_t)1 << 32)) return SDD_EINVAL;
     if (!(dt > 0.0) || !(dt < 1.0)) return SDD_EINVAL;
     if (prec != SDD_FP32 && prec != SDD_FP64) return SDD_EINVAL;
     if (!(t_max > 0.0)) t_max = 8.0;
     if (!is_finite(t_max)) return SDD_EINVAL;
-    const double kd = ceil(t_max / dt);
+    double kd = ceil(t_max / dt);
     if (!(kd >= 1.0) || kd >= 2147483640.0) return SDD_EINVAL;
-    if (ws_bytes < sdd_workspace_bytes(n_nodes, paths_per_node, prec)) return SDD_ENOSPC;
+    kd += fmod(kd, 2.0);  // the cap is rounded up to an even step count
+    const WalkWorkspace W = walk_workspace(n_nodes, paths_per_node, prec);
+    if (ws_bytes < W.bytes) return SDD_ENOSPC;
     if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
 
     WalkArgs A;
@@ -198,19 +199,19 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
     A.n_nodes = n_nodes;
     A.paths = paths_per_node;
     A.path_begin = path_begin;
-    A.chunk = walk_chunk(n_nodes, paths_per_node);
-    A.n_chunks = (paths_per_node + A.chunk - 1) / A.chunk;
-    A.n_items = n_nodes * A.n_chunks;
+    A.total = (uint32_t)(n_nodes * paths_per_node);
+    A.kmax = (int32_t)kd;
     A.dt = dt;
     A.sqrt2dt = sqrt(2.0 * dt);
-    A.kmax = (int32_t)kd;
+    A.noise_f32 = sqrt(2.0 * dt) * sqrt(2.0 * 0.69314718055994530942);
     A.key0 = (uint32_t)seed;
     A.key1 = (uint32_t)(seed >> 32);
     char* ws = (char*)workspace;
-    A.slots = (Slot*)ws;
-    long long* node_tot = (long long*)(ws + align_up((size_t)A.n_items * sizeof(Slot), 256));
+    A.pq = (void*)(ws + W.pq_off);
+    A.info = (uint32_t*)(ws + W.info_off);
+    A.counter = (unsigned long long*)(ws + W.counter_off);
     A.per_path = per_path;
-    if (A.n_items / 4 + 1 > 0x7fffffff) return SDD_EINVAL;
+    long long* node_tot = (long long*)(ws + W.node_tot_off);
     return from_hip(launch_walk(A, prec, mean, se, sums, stats, node_tot, (hipStream_t)stream));
 }
 

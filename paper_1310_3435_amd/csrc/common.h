@@ -33,6 +33,8 @@ struct Density {
     float fbase;
     float famp[SDD_MAX_TERMS], fcoef[SDD_MAX_TERMS], fk2[SDD_MAX_TERMS], fcx[SDD_MAX_TERMS];
     float fcy[SDD_MAX_TERMS], fr0[SDD_MAX_TERMS], fnx[SDD_MAX_TERMS], fny[SDD_MAX_TERMS];
+    // la = log2(amp) (amp e^{-c t} = 2^(k2 t + la)), m2c = -2 coef
+    float fla[SDD_MAX_TERMS], fm2c[SDD_MAX_TERMS];
 };
 
 struct Bmap {
@@ -44,54 +46,69 @@ struct Bmap {
 
 // ------------------------------------------------------------------ density
 
-// w and grad w in double (parity mode and the deterministic kernels).
+// One density term's value and gradient added into (W, Gx, Gy), double.
+template <int KIND>
+__device__ inline void term_f64(const Density& D, int t, double xi, double eta, double& W, double& Gx, double& Gy)
+{
+    const double dx = xi - D.cx[t], dy = eta - D.cy[t];
+    const double a = D.amp[t], c = D.coef[t];
+    if (KIND == SDD_TERM_GAUSS) {
+        const double e = a * exp(-c * (dx * dx + dy * dy));
+        W += e;
+        const double g = -2.0 * c * e;
+        Gx += g * dx;
+        Gy += g * dy;
+    } else if (KIND == SDD_TERM_RING) {
+        const double r = sqrt(dx * dx + dy * dy);
+        const double d = r - D.r0[t];
+        const double e = a * exp(-c * d * d);
+        W += e;
+        if (r > 0.0) {
+            const double g = -2.0 * c * d * e / r;
+            Gx += g * dx;
+            Gy += g * dy;
+        }
+    } else if (KIND == SDD_TERM_SECH2) {
+        // sech^2 s = 4q/(1+q)^2, tanh s = sign(s)(1-q)/(1+q), q = e^{-2|s|}
+        const double s = c * (D.nx[t] * dx + D.ny[t] * dy);
+        const double q = exp(-2.0 * fabs(s));
+        const double inv = 1.0 / (1.0 + q);
+        const double f = a * 4.0 * q * inv * inv;
+        const double th = copysign((1.0 - q) * inv, s);
+        W += f;
+        const double g = -2.0 * f * th * c;
+        Gx += g * D.nx[t];
+        Gy += g * D.ny[t];
+    } else if (KIND == SDD_TERM_SIN2) {
+        const double s = c * (D.nx[t] * dx + D.ny[t] * dy);
+        double sn, cs;
+        sincos(s, &sn, &cs);
+        W += a * sn * sn;
+        const double g = 2.0 * a * sn * cs * c;
+        Gx += g * D.nx[t];
+        Gy += g * D.ny[t];
+    }
+}
+
+// w and grad w in double.  KIND >= 0: a single term of that kind (known at
+// compile time); KIND = kAnyTerms: the general sum over D.n_terms terms.
+constexpr int kAnyTerms = -1;
+
+template <int KIND = kAnyTerms>
 __device__ inline void density_grad(const Density& D, double xi, double eta, double& w, double& gx, double& gy)
 {
     double W = D.base, Gx = 0.0, Gy = 0.0;
-    for (int t = 0; t < D.n_terms; ++t) {
-        const double dx = xi - D.cx[t], dy = eta - D.cy[t];
-        const double a = D.amp[t], c = D.coef[t];
-        switch (D.kind[t]) {
-        case SDD_TERM_GAUSS: {
-            const double e = a * exp(-c * (dx * dx + dy * dy));
-            W += e;
-            const double g = -2.0 * c * e;
-            Gx += g * dx;
-            Gy += g * dy;
-        } break;
-        case SDD_TERM_RING: {
-            const double r = sqrt(dx * dx + dy * dy);
-            const double d = r - D.r0[t];
-            const double e = a * exp(-c * d * d);
-            W += e;
-            if (r > 0.0) {
-                const double g = -2.0 * c * d * e / r;
-                Gx += g * dx;
-                Gy += g * dy;
+    if (KIND >= 0) {
+        term_f64<KIND>(D, 0, xi, eta, W, Gx, Gy);
+    } else {
+        for (int t = 0; t < D.n_terms; ++t) {
+            switch (D.kind[t]) {
+            case SDD_TERM_GAUSS: term_f64<SDD_TERM_GAUSS>(D, t, xi, eta, W, Gx, Gy); break;
+            case SDD_TERM_RING: term_f64<SDD_TERM_RING>(D, t, xi, eta, W, Gx, Gy); break;
+            case SDD_TERM_SECH2: term_f64<SDD_TERM_SECH2>(D, t, xi, eta, W, Gx, Gy); break;
+            case SDD_TERM_SIN2: term_f64<SDD_TERM_SIN2>(D, t, xi, eta, W, Gx, Gy); break;
+            default: break;
             }
-        } break;
-        case SDD_TERM_SECH2: {
-            // sech^2 s = 4q/(1+q)^2, tanh s = sign(s)(1-q)/(1+q), q = e^{-2|s|}
-            const double s = c * (D.nx[t] * dx + D.ny[t] * dy);
-            const double q = exp(-2.0 * fabs(s));
-            const double inv = 1.0 / (1.0 + q);
-            const double f = a * 4.0 * q * inv * inv;
-            const double th = copysign((1.0 - q) * inv, s);
-            W += f;
-            const double g = -2.0 * f * th * c;
-            Gx += g * D.nx[t];
-            Gy += g * D.ny[t];
-        } break;
-        case SDD_TERM_SIN2: {
-            const double s = c * (D.nx[t] * dx + D.ny[t] * dy);
-            double sn, cs;
-            sincos(s, &sn, &cs);
-            W += a * sn * sn;
-            const double g = 2.0 * a * sn * cs * c;
-            Gx += g * D.nx[t];
-            Gy += g * D.ny[t];
-        } break;
-        default: break;
         }
     }
     w = W;
@@ -106,55 +123,113 @@ __device__ inline double density_value(const Density& D, double xi, double eta)
     return w;
 }
 
-// drift b = grad w / w in float, on the transcendental unit.
+// One term in float, on the transcendental unit.
+template <int KIND>
+__device__ inline void term_f32(const Density& D, int t, float xi, float eta, float& W, float& Gx, float& Gy)
+{
+    const float dx = xi - D.fcx[t], dy = eta - D.fcy[t];
+    const float a = D.famp[t], c = D.fcoef[t];
+    if (KIND == SDD_TERM_GAUSS) {
+        const float e = a * __builtin_amdgcn_exp2f(D.fk2[t] * (dx * dx + dy * dy));
+        W += e;
+        const float g = -2.0f * c * e;
+        Gx += g * dx;
+        Gy += g * dy;
+    } else if (KIND == SDD_TERM_RING) {
+        const float r2 = dx * dx + dy * dy;
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float r = (r2 > 0.0f) ? r2 * rinv : 0.0f;  // rsq(0) = inf
+        const float d = r - D.fr0[t];
+        const float e = a * __builtin_amdgcn_exp2f(D.fk2[t] * d * d);
+        W += e;
+        const float g = (r2 > 0.0f) ? (-2.0f * c * d * e * rinv) : 0.0f;
+        Gx += g * dx;
+        Gy += g * dy;
+    } else if (KIND == SDD_TERM_SECH2) {
+        const float s = c * (D.fnx[t] * dx + D.fny[t] * dy);
+        const float q = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(s));
+        const float inv = __builtin_amdgcn_rcpf(1.0f + q);
+        const float f = a * 4.0f * q * inv * inv;
+        const float th = copysignf((1.0f - q) * inv, s);
+        W += f;
+        const float g = -2.0f * f * th * c;
+        Gx += g * D.fnx[t];
+        Gy += g * D.fny[t];
+    } else if (KIND == SDD_TERM_SIN2) {
+        const float s = c * (D.fnx[t] * dx + D.fny[t] * dy);
+        float turns = s * kInvTwoPi;
+        turns = turns - floorf(turns);
+        const float sn = __builtin_amdgcn_sinf(turns);
+        const float cs = __builtin_amdgcn_cosf(turns);
+        W += a * sn * sn;
+        const float g = 2.0f * a * sn * cs * c;
+        Gx += g * D.fnx[t];
+        Gy += g * D.fny[t];
+    }
+}
+
+// drift b = grad w / w in float for a single term, written so that the
+// amplitude folds into the exponent and 1/w into one common factor h with
+// b = h (d_xi, d_eta) or b = h (nx, ny).
+template <int KIND>
+__device__ inline void drift1_f32(const Density& D, float xi, float eta, float& bx, float& by)
+{
+    const float dx = xi - D.fcx[0], dy = eta - D.fcy[0];
+    if (KIND == SDD_TERM_GAUSS) {
+        const float r2 = __builtin_fmaf(dx, dx, dy * dy);
+        const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(D.fk2[0], r2, D.fla[0]));
+        const float h = D.fm2c[0] * e * __builtin_amdgcn_rcpf(D.fbase + e);
+        bx = h * dx;
+        by = h * dy;
+    } else if (KIND == SDD_TERM_RING) {
+        // r^2 clamped away from 0: at the centre d_xi = d_eta = 0 and b = 0
+        const float r2 = fmaxf(__builtin_fmaf(dx, dx, dy * dy), 1e-30f);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float d = __builtin_fmaf(r2, rinv, -D.fr0[0]);
+        const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(D.fk2[0] * d, d, D.fla[0]));
+        const float h = D.fm2c[0] * d * e * rinv * __builtin_amdgcn_rcpf(D.fbase + e);
+        bx = h * dx;
+        by = h * dy;
+    } else if (KIND == SDD_TERM_SECH2) {
+        const float s = D.fcoef[0] * __builtin_fmaf(D.fnx[0], dx, D.fny[0] * dy);
+        const float q = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(s));
+        const float inv = __builtin_amdgcn_rcpf(1.0f + q);
+        const float f = D.famp[0] * 4.0f * q * inv * inv;
+        const float th = copysignf((1.0f - q) * inv, s);
+        const float h = D.fm2c[0] * f * th * __builtin_amdgcn_rcpf(D.fbase + f);
+        bx = h * D.fnx[0];
+        by = h * D.fny[0];
+    } else {  // SIN2
+        const float s = D.fcoef[0] * __builtin_fmaf(D.fnx[0], dx, D.fny[0] * dy);
+        float turns = s * kInvTwoPi;
+        turns = turns - floorf(turns);
+        const float sn = __builtin_amdgcn_sinf(turns);
+        const float cs = __builtin_amdgcn_cosf(turns);
+        const float f = D.famp[0] * sn * sn;
+        const float h = -D.fm2c[0] * D.famp[0] * sn * cs * __builtin_amdgcn_rcpf(D.fbase + f);
+        bx = h * D.fnx[0];
+        by = h * D.fny[0];
+    }
+}
+
+// drift b = grad w / w in float.
+template <int KIND = kAnyTerms>
 __device__ inline void drift_f32(const Density& D, float xi, float eta, float& bx, float& by)
 {
+    if (KIND >= 0) {
+        drift1_f32<KIND>(D, xi, eta, bx, by);
+        return;
+    }
     float W = D.fbase, Gx = 0.0f, Gy = 0.0f;
-    for (int t = 0; t < D.n_terms; ++t) {
-        const float dx = xi - D.fcx[t], dy = eta - D.fcy[t];
-        const float a = D.famp[t], c = D.fcoef[t];
-        switch (D.kind[t]) {
-        case SDD_TERM_GAUSS: {
-            const float e = a * __builtin_amdgcn_exp2f(D.fk2[t] * (dx * dx + dy * dy));
-            W += e;
-            const float g = -2.0f * c * e;
-            Gx += g * dx;
-            Gy += g * dy;
-        } break;
-        case SDD_TERM_RING: {
-            const float r2 = dx * dx + dy * dy;
-            const float rinv = __builtin_amdgcn_rsqf(r2);
-            const float r = (r2 > 0.0f) ? r2 * rinv : 0.0f;  // rsq(0) = inf
-            const float d = r - D.fr0[t];
-            const float e = a * __builtin_amdgcn_exp2f(D.fk2[t] * d * d);
-            W += e;
-            const float g = (r2 > 0.0f) ? (-2.0f * c * d * e * rinv) : 0.0f;
-            Gx += g * dx;
-            Gy += g * dy;
-        } break;
-        case SDD_TERM_SECH2: {
-            const float s = c * (D.fnx[t] * dx + D.fny[t] * dy);
-            const float q = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(s));
-            const float inv = __builtin_amdgcn_rcpf(1.0f + q);
-            const float f = a * 4.0f * q * inv * inv;
-            const float th = copysignf((1.0f - q) * inv, s);
-            W += f;
-            const float g = -2.0f * f * th * c;
-            Gx += g * D.fnx[t];
-            Gy += g * D.fny[t];
-        } break;
-        case SDD_TERM_SIN2: {
-            const float s = c * (D.fnx[t] * dx + D.fny[t] * dy);
-            float turns = s * kInvTwoPi;
-            turns = turns - floorf(turns);
-            const float sn = __builtin_amdgcn_sinf(turns);
-            const float cs = __builtin_amdgcn_cosf(turns);
-            W += a * sn * sn;
-            const float g = 2.0f * a * sn * cs * c;
-            Gx += g * D.fnx[t];
-            Gy += g * D.fny[t];
-        } break;
-        default: break;
+    {
+        for (int t = 0; t < D.n_terms; ++t) {
+            switch (D.kind[t]) {
+            case SDD_TERM_GAUSS: term_f32<SDD_TERM_GAUSS>(D, t, xi, eta, W, Gx, Gy); break;
+            case SDD_TERM_RING: term_f32<SDD_TERM_RING>(D, t, xi, eta, W, Gx, Gy); break;
+            case SDD_TERM_SECH2: term_f32<SDD_TERM_SECH2>(D, t, xi, eta, W, Gx, Gy); break;
+            case SDD_TERM_SIN2: term_f32<SDD_TERM_SIN2>(D, t, xi, eta, W, Gx, Gy); break;
+            default: break;
+            }
         }
     }
     const float iw = __builtin_amdgcn_rcpf(W);
@@ -162,10 +237,11 @@ __device__ inline void drift_f32(const Density& D, float xi, float eta, float& b
     by = Gy * iw;
 }
 
+template <int KIND = kAnyTerms>
 __device__ inline void drift_f64(const Density& D, double xi, double eta, double& bx, double& by)
 {
     double w, gx, gy;
-    density_grad(D, xi, eta, w, gx, gy);
+    density_grad<KIND>(D, xi, eta, w, gx, gy);
     bx = gx / w;
     by = gy / w;
 }

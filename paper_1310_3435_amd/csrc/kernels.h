@@ -9,14 +9,9 @@
 
 namespace sdd {
 
-// Per-item partial sums written by the walk: sum x, sum y, sum x^2, sum y^2,
-// step total and capped count of one (node, chunk) work item.
-struct Slot {
-    double s[4];
-    long long steps;
-    long long capped;
-};
-
+// Walk launch arguments.  Path tickets t = g * paths + (p - path_begin)
+// enumerate every (node g, path p) pair; a persistent grid of waves draws
+// them from a device counter.
 struct WalkArgs {
     Density dens;
     Bmap bmap;
@@ -24,20 +19,23 @@ struct WalkArgs {
     int64_t n_nodes;
     int64_t paths;       // N per node
     int64_t path_begin;  // counter word of the first path
-    int64_t chunk;       // paths per work item
-    int64_t n_chunks;    // work items per node
-    int64_t n_items;     // n_nodes * n_chunks
+    uint32_t total;      // n_nodes * paths (< 2^32)
+    int32_t kmax;
     double dt;
     double sqrt2dt;
-    int32_t kmax;
+    double noise_f32;    // sqrt(2 dt) sqrt(2 ln 2): the float walk's normals come scaled
     uint32_t key0, key1;
-    Slot* slots;
-    sdd_path_record* per_path;
+    void* pq;                     // [total] (P.x, P.y, Q.x, Q.y) of the last step, walk precision
+    uint32_t* info;               // [total] exit step | capped << 31
+    unsigned long long* counter;  // ticket counter, zeroed before the walk
+    sdd_path_record* per_path;    // optional [total]
 };
 
-// Paths per work item for a given problem size; fixed by (n_nodes, paths)
-// alone so that results do not depend on the device.
-int64_t walk_chunk(int64_t n_nodes, int64_t paths);
+// Workspace carving of sdd_interface_estimate.
+struct WalkWorkspace {
+    size_t pq_off, info_off, counter_off, node_tot_off, bytes;
+};
+WalkWorkspace walk_workspace(int64_t n_nodes, int64_t paths, int prec);
 
 hipError_t launch_walk(const WalkArgs& A, int prec, double* mean, double* se, double* sums, sdd_walk_stats* stats,
                        long long* node_tot, hipStream_t stream);

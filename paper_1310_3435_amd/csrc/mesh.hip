@@ -465,6 +465,8 @@ __global__ __launch_bounds__(kSorBlock) void sor_kernel(sdd_layout L, const doub
     const int ncand = half * (my - 1);
     int sweep = 0;
     double last = 0.0;
+    double best = __builtin_inf();  // thread 0 only
+    int since = 0;                  // checks since the last halving of the change
     while (sweep < max_sweeps) {
         double dmax = 0.0;
         for (int colour = 0; colour < 2; ++colour) {
@@ -493,7 +495,15 @@ __global__ __launch_bounds__(kSorBlock) void sor_kernel(sdd_layout L, const doub
                 double r = 0.0;
                 for (int i = 0; i < (int)(blockDim.x / kWave); ++i) r = fmax(r, red[i]);
                 last = r;
-                stop = (r <= tol) ? 1 : 0;
+                // converged, or stalled at the rounding floor: no halving of
+                // the largest change within 64 checks
+                if (r < 0.5 * best) {
+                    best = r;
+                    since = 0;
+                } else {
+                    ++since;
+                }
+                stop = (r <= tol || since >= 64) ? 1 : 0;
                 red[0] = r;
             }
             __syncthreads();

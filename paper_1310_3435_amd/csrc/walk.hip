@@ -1,19 +1,21 @@
 // walk.hip -- interface Monte Carlo walk (gfx950).
 //
-// Each wavefront owns one work item: a node g and a chunk of consecutive
-// path indices.  One lane walks one path at a time; when its path exits the
-// lane takes the chunk's next unassigned path (ballot + mbcnt, so the
-// assignment is the same on every run).  A loop iteration is one Philox
-// block, i.e. two Euler-Maruyama steps (Sec. 2.2) with an exit test after
-// each; a path always starts at an even step, so every lane consumes its
-// four random words in the same iteration.  At exit the step's segment is
-// projected onto the boundary in double, the boundary map is evaluated there
-// (eq. (7a)) and the value enters the lane's compensated double sums.  The
-// wave reduces its lanes with cross-lane shuffles and writes one slot per
-// item; the finalize kernel adds a node's slots in chunk order.
+// A persistent grid of wavefronts draws path tickets (node g, path p) from a
+// device counter, 64 at a time per wave.  One lane walks one path; when its
+// path exits, the lane takes the wave's next ticket, whatever node it
+// belongs to, so lanes stay busy until the ticket range is exhausted.  A
+// loop iteration is one Philox block, i.e. two Euler-Maruyama steps (Sec.
+// 2.2) with an exit test after each; a path always starts at an even step.
+// At exit the lane stores the last step's endpoints P, Q and the step count
+// in the path's own slot.  A second kernel projects P -> Q onto the boundary
+// in double, evaluates the boundary map there (eq. (7a)) and reduces each
+// node's paths in a fixed order, so every result is independent of the
+// schedule, and the walk keeps no double-precision state.
 //
-// Nothing on the walk path touches HBM except the node read at the start
-// and the slot write at the end (plus optional per-path records).
+// The walk itself touches HBM only to read a node at path start and to
+// write 20 bytes (float walk) or 36 bytes (double walk) per finished path.
+#include <stdlib.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -24,7 +26,13 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
-// Philox4x32-10 (Salmon et al., SC'11).  The key schedule is wave-uniform.
+// Philox4x32-10 (Salmon et al., SC'11).  The key schedule is wave-uniform;
+// each three-input XOR is one v_bitop3_b32 (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                         uint32_t k1)
 {
@@ -32,8 +40,8 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -44,22 +52,31 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
-// Box-Muller pair from two words: u = ((r >> 9) + 1/2) 2^-23 (exact in both
-// precisions), (z0, z1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
+// Uniform from the low 23 bits of a word: u = ((r & 0x7fffff) + 1/2) 2^-23,
+// exact in float and double.  In float it is built as the bit pattern
+// 1 + m 2^-23 (one v_and_or_b32) minus (1 - 2^-24), an exact subtraction.
+__device__ __forceinline__ float uniform_f32(uint32_t r)
+{
+    return __uint_as_float((r & 0x007fffffu) | 0x3f800000u) - 0x1.fffffep-1f;
+}
+
+// Box-Muller pair (z0, z1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
+// The float version returns the pair scaled by 1/sqrt(2 ln 2),
+// sqrt(-log2 u_a) (cos, sin), and the caller folds sqrt(2 ln 2) into the
+// step's noise factor; v_sin/v_cos take their argument in turns.
 __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, float& z0, float& z1)
 {
-    const float ua = __builtin_fmaf((float)(ra >> 9), 0x1p-23f, 0x1p-24f);
-    const float ub = __builtin_fmaf((float)(rb >> 9), 0x1p-23f, 0x1p-24f);
-    // -2 ln u = -2 ln2 log2 u
-    const float radius = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+    const float ua = uniform_f32(ra);
+    const float ub = uniform_f32(rb);
+    const float radius = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(ua));
     z0 = radius * __builtin_amdgcn_cosf(ub);
     z1 = radius * __builtin_amdgcn_sinf(ub);
 }
 
 __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, double& z0, double& z1)
 {
-    const double ua = ((double)(ra >> 9) + 0.5) * 0x1p-23;
-    const double ub = ((double)(rb >> 9) + 0.5) * 0x1p-23;
+    const double ua = ((double)(ra & 0x007fffffu) + 0.5) * 0x1p-23;
+    const double ub = ((double)(rb & 0x007fffffu) + 0.5) * 0x1p-23;
     const double radius = sqrt(-2.0 * log(ua));
     double sn, cs;
     sincos(kTwoPi * ub, &sn, &cs);
@@ -67,193 +84,243 @@ __device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, double& z0, do
     z1 = radius * sn;
 }
 
+// Noise factor of one step: sqrt(2 dt) times the normals' scale above.
+__device__ __forceinline__ float noise_scale(const WalkArgs& A, float) { return (float)A.noise_f32; }
+__device__ __forceinline__ double noise_scale(const WalkArgs& A, double) { return A.sqrt2dt; }
+
+template <int KIND>
 __device__ __forceinline__ void drift(const Density& D, float x, float y, float& bx, float& by)
 {
-    drift_f32(D, x, y, bx, by);
+    drift_f32<KIND>(D, x, y, bx, by);
 }
+template <int KIND>
 __device__ __forceinline__ void drift(const Density& D, double x, double y, double& bx, double& by)
 {
-    drift_f64(D, x, y, bx, by);
+    drift_f64<KIND>(D, x, y, bx, by);
 }
 
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-__device__ __forceinline__ bool outside(float x, float y) { return x <= 0.0f || x >= 1.0f || y <= 0.0f || y >= 1.0f; }
+// Outside the open square: x <= 0, x >= 1 (or NaN) for either coordinate.
+// For a float, 0 < x < 1 exactly when its bit pattern minus one is below
+// that of 1.0f minus one (unsigned), which costs no NaN canonicalisation.
+__device__ __forceinline__ bool outside(float x, float y)
+{
+    const uint32_t bx = __float_as_uint(x) - 1u, by = __float_as_uint(y) - 1u;
+    return (bx > by ? bx : by) >= 0x3f7fffffu;
+}
 __device__ __forceinline__ bool outside(double x, double y) { return x <= 0.0 || x >= 1.0 || y <= 0.0 || y >= 1.0; }
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, kWave); }
 __device__ __forceinline__ long long shfl_xor_l(long long v, int m) { return __shfl_xor(v, m, kWave); }
 
-template <typename R>
-__global__ __launch_bounds__(256) void walk_kernel(const WalkArgs A)
+__device__ __forceinline__ void store_pq(const WalkArgs& A, uint32_t t, float px, float py, float qx, float qy)
+{
+    reinterpret_cast<float4*>(A.pq)[t] = make_float4(px, py, qx, qy);
+}
+__device__ __forceinline__ void store_pq(const WalkArgs& A, uint32_t t, double px, double py, double qx, double qy)
+{
+    double2* d = reinterpret_cast<double2*>(A.pq) + 2 * (size_t)t;
+    d[0] = make_double2(px, py);
+    d[1] = make_double2(qx, qy);
+}
+
+__device__ __forceinline__ void load_pq(const void* pq, size_t t, float, double& px, double& py, double& qx,
+                                        double& qy)
+{
+    const float4 v = reinterpret_cast<const float4*>(pq)[t];
+    px = v.x; py = v.y; qx = v.z; qy = v.w;
+}
+__device__ __forceinline__ void load_pq(const void* pq, size_t t, double, double& px, double& py, double& qx,
+                                        double& qy)
+{
+    const double2* d = reinterpret_cast<const double2*>(pq) + 2 * t;
+    px = d[0].x; py = d[0].y; qx = d[1].x; qy = d[1].y;
+}
+
+constexpr uint32_t kTicketBatch = 64;
+constexpr int kWalkBlock = 256;
+
+template <typename R, int KIND>
+__global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
 {
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-    if (item >= A.n_items) return;  // whole wave
-    const int64_t g = item / A.n_chunks;
-    const int64_t chunk = item - g * A.n_chunks;
-    const int64_t p_lo = chunk * A.chunk;
-    const int32_t count = (int32_t)min((int64_t)A.chunk, A.paths - p_lo);
-    Slot* slot = A.slots + item;
-
-    const double node_x = A.nodes[2 * g], node_y = A.nodes[2 * g + 1];
-    if (!(node_x > 0.0 && node_x < 1.0 && node_y > 0.0 && node_y < 1.0)) {
-        if (lane == 0) {
-            const double nan = __builtin_nan("");
-            slot->s[0] = slot->s[1] = slot->s[2] = slot->s[3] = nan;
-            slot->steps = 0;
-            slot->capped = 0;
-        }
-        return;
-    }
-    const R x0 = (R)node_x, y0 = (R)node_y;
+    const uint32_t N = (uint32_t)A.paths;
     const R dt = (R)A.dt;
-    const R sd = (R)A.sqrt2dt;
-    const uint32_t gw = (uint32_t)g;
-    const uint32_t pbase = (uint32_t)(A.path_begin + p_lo);
+    const R sd = noise_scale(A, R(0));
 
-    int32_t pl = lane;  // path index within the chunk
-    bool live = pl < count;
-    R X = x0, Y = y0;
+    // wave-uniform ticket pool
+    uint32_t pool_lo = 0, pool_hi = 0;
+    bool exhausted = false;
+    // lane state
+    bool live = false;
+    uint32_t t = 0, g = 0, pc = 0;  // ticket, node, path counter word
+    R X = 0, Y = 0;
     int32_t k = 0;
-    int32_t next = kWave;
 
-    double sx = 0, cx = 0, sy = 0, cy = 0, sxx = 0, cxx = 0, syy = 0, cyy = 0;
-    long long nsteps = 0;
-    int32_t ncapped = 0;
+    for (;;) {
+        // hand the wave's tickets to idle lanes, in lane order
+        uint64_t need = __ballot(!live);
+        while (need != 0 && !exhausted) {
+            if (pool_lo == pool_hi) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(A.counter, (unsigned long long)kTicketBatch);
+                base = __shfl(base, 0, kWave);
+                if (base >= A.total) {
+                    exhausted = true;
+                    break;
+                }
+                pool_lo = (uint32_t)base;
+                pool_hi = (uint32_t)min((unsigned long long)A.total, base + kTicketBatch);
+            }
+            const uint32_t avail = pool_hi - pool_lo;
+            const uint32_t want = (uint32_t)__popcll(need);
+            const uint32_t take = want < avail ? want : avail;
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!live && rank < take) {
+                t = pool_lo + rank;
+                g = t / N;
+                pc = (uint32_t)A.path_begin + (t - g * N);
+                const double nx0 = A.nodes[2 * (size_t)g], ny0 = A.nodes[2 * (size_t)g + 1];
+                if (nx0 > 0.0 && nx0 < 1.0 && ny0 > 0.0 && ny0 < 1.0) {
+                    X = (R)nx0;
+                    Y = (R)ny0;
+                    k = 0;
+                    live = true;
+                } else {
+                    // a node off the open square walks nothing: NaN result
+                    const R nan = (R)__builtin_nan("");
+                    store_pq(A, t, nan, nan, nan, nan);
+                    A.info[t] = 0;
+                }
+            }
+            pool_lo += take;
+            need = __ballot(!live);
+        }
+        if (__ballot(live) == 0) break;
 
-    while (__ballot(live) != 0) {
-        const uint4 r = philox((uint32_t)(k >> 1), pbase + (uint32_t)pl, gw, 0u, A.key0, A.key1);
+        const uint4 r = philox((uint32_t)(k >> 1), pc, g, 0u, A.key0, A.key1);
         R bx, by, z0, z1;
         // step 2m
         normals(r.x, r.y, z0, z1);
-        drift(A.dens, X, Y, bx, by);
+        drift<KIND>(A.dens, X, Y, bx, by);
         const R XA = fmar(sd, z0, fmar(bx, dt, X));
         const R YA = fmar(sd, z1, fmar(by, dt, Y));
         // step 2m+1
         normals(r.z, r.w, z0, z1);
-        drift(A.dens, XA, YA, bx, by);
+        drift<KIND>(A.dens, XA, YA, bx, by);
         const R XB = fmar(sd, z0, fmar(bx, dt, XA));
         const R YB = fmar(sd, z1, fmar(by, dt, YA));
 
+        // the step cap is even, so it can only fall after step 2m+1
         const bool outA = outside(XA, YA);
-        const bool endA = outA || (k + 1 >= A.kmax);
         const bool outB = outside(XB, YB);
-        const bool fin = live && (endA || outB || (k + 2 >= A.kmax));
+        const bool fin = live && (outA || outB || (k + 2 >= A.kmax));
 
-        const uint64_t fmask = __ballot(fin);
-        if (fmask != 0) {
-            if (fin) {
-                double px, py, qx, qy, ex, ey;
-                int32_t steps, side, capped;
-                bool exited;
-                if (endA) {
-                    px = (double)X; py = (double)Y; qx = (double)XA; qy = (double)YA;
-                    steps = k + 1;
-                    exited = outA;
-                } else {
-                    px = (double)XA; py = (double)YA; qx = (double)XB; qy = (double)YB;
-                    steps = k + 2;
-                    exited = outB;
-                }
-                if (exited) {
-                    side = exit_point(px, py, qx, qy, ex, ey);
-                    capped = 0;
-                } else {
-                    side = nearest_side(qx, qy, ex, ey);
-                    capped = 1;
-                }
-                double vx, vy;
-                bmap_eval(A.bmap, side, ex, ey, vx, vy);
-                nadd(sx, cx, vx);
-                nadd(sy, cy, vy);
-                nadd(sxx, cxx, vx * vx);
-                nadd(syy, cyy, vy * vy);
-                nsteps += steps;
-                ncapped += capped;
-                if (A.per_path) {
-                    sdd_path_record* rec = A.per_path + g * A.paths + (p_lo + pl);
-                    rec->exit_xi = ex;
-                    rec->exit_eta = ey;
-                    rec->steps = steps;
-                    rec->side = side;
-                    rec->capped = capped;
-                }
-            }
-            // refill finished lanes with the chunk's next paths, in lane order
-            const uint32_t rank =
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(fmask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fmask, 0u));
-            if (fin) {
-                const int32_t np = next + (int32_t)rank;
-                if (np < count) {
-                    pl = np;
-                    X = x0;
-                    Y = y0;
-                    k = 0;
-                } else {
-                    live = false;
-                }
-            }
-            next += __popcll(fmask);
+        if (fin) {
+            // the exit projection and boundary map run in the reduction
+            if (outA)
+                store_pq(A, t, X, Y, XA, YA);
+            else
+                store_pq(A, t, XA, YA, XB, YB);
+            A.info[t] = (uint32_t)(outA ? k + 1 : k + 2) | ((outA || outB) ? 0u : 0x80000000u);
+            live = false;
         }
-        if (live && !fin) {
-            X = XB;
-            Y = YB;
-            k += 2;
-        }
-    }
-
-    // wave reduction of the lane sums
-    double v[4] = { sx + cx, sy + cy, sxx + cxx, syy + cyy };
-    long long st = nsteps;
-    long long cp = ncapped;
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += shfl_xor_d(v[q], m);
-        st += shfl_xor_l(st, m);
-        cp += shfl_xor_l(cp, m);
-    }
-    if (lane == 0) {
-        slot->s[0] = v[0];
-        slot->s[1] = v[1];
-        slot->s[2] = v[2];
-        slot->s[3] = v[3];
-        slot->steps = st;
-        slot->capped = cp;
+        // finished and idle lanes carry garbage until their next start
+        X = XB;
+        Y = YB;
+        k += 2;
     }
 }
 
-// One thread per node: slots in chunk order, compensated; mean, SE, sums.
-__global__ void finalize_kernel(const Slot* __restrict__ slots, int64_t n_nodes, int64_t n_chunks, int64_t paths,
-                                double* __restrict__ mean, double* __restrict__ se, double* __restrict__ sums,
-                                long long* __restrict__ node_tot)
+__global__ void reset_counter_kernel(unsigned long long* counter) { *counter = 0ull; }
+
+constexpr int kReduceBlock = 256;
+
+__device__ __forceinline__ uint32_t in_info(const uint32_t* info, size_t t) { return info[t]; }
+
+// One block per node.  Each path's last step P -> Q is projected onto the
+// boundary in double (first crossing; nearest boundary point for a capped
+// path) and mapped through the boundary map; the node's values are summed in
+// a fixed order (thread j takes paths j, j+256, ... with compensated sums,
+// then a fixed tree), so results do not depend on how the walk was
+// scheduled.
+template <typename R>
+__global__ __launch_bounds__(kReduceBlock) void reduce_kernel(const void* __restrict__ pq,
+                                                              const uint32_t* __restrict__ info, int64_t paths,
+                                                              const Bmap B, double* __restrict__ mean,
+                                                              double* __restrict__ se, double* __restrict__ sums,
+                                                              long long* __restrict__ node_tot,
+                                                              sdd_path_record* __restrict__ per_path)
 {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_nodes) return;
+    __shared__ double part[4][kReduceBlock / kWave];
+    __shared__ long long ipart[2][kReduceBlock / kWave];
+    const int64_t g = blockIdx.x;
     double s[4] = { 0, 0, 0, 0 }, c[4] = { 0, 0, 0, 0 };
     long long st = 0, cp = 0;
-    for (int64_t j = 0; j < n_chunks; ++j) {
-        const Slot& S = slots[g * n_chunks + j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nadd(s[q], c[q], S.s[q]);
-        st += S.steps;
-        cp += S.capped;
+    for (int64_t j = threadIdx.x; j < paths; j += kReduceBlock) {
+        const size_t t = (size_t)(g * paths + j);
+        double px, py, qx, qy, ex, ey;
+        load_pq(pq, t, R(0), px, py, qx, qy);
+        const uint32_t w = in_info(info, t);
+        const bool capped = (w >> 31) != 0;
+        const int side = capped ? nearest_side(qx, qy, ex, ey) : exit_point(px, py, qx, qy, ex, ey);
+        double x, y;
+        bmap_eval(B, side, ex, ey, x, y);
+        if (px != px) x = y = px;  // node off the square: NaN
+        nadd(s[0], c[0], x);
+        nadd(s[1], c[1], y);
+        nadd(s[2], c[2], x * x);
+        nadd(s[3], c[3], y * y);
+        st += w & 0x7fffffffu;
+        cp += w >> 31;
+        if (per_path) {
+            sdd_path_record* rec = per_path + t;
+            rec->exit_xi = ex;
+            rec->exit_eta = ey;
+            rec->steps = w & 0x7fffffffu;
+            rec->side = side;
+            rec->capped = capped ? 1 : 0;
+        }
     }
     double tot[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) tot[q] = s[q] + c[q];
-    const double N = (double)paths;
-    const double mx = tot[0] / N, my = tot[1] / N;
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tot[q] += shfl_xor_d(tot[q], m);
+        st += shfl_xor_l(st, m);
+        cp += shfl_xor_l(cp, m);
+    }
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[q][w] = tot[q];
+        ipart[0][w] = st;
+        ipart[1][w] = cp;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double T[4] = { 0, 0, 0, 0 };
+    long long ST = 0, CP = 0;
+    for (int i = 0; i < kReduceBlock / kWave; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) T[q] += part[q][i];
+        ST += ipart[0][i];
+        CP += ipart[1][i];
+    }
+    const double Nd = (double)paths;
+    const double mx = T[0] / Nd, my = T[1] / Nd;
     mean[2 * g] = mx;
     mean[2 * g + 1] = my;
     if (se) {
         if (paths > 1) {
-            const double vx = tot[2] - N * mx * mx, vy = tot[3] - N * my * my;
-            se[2 * g] = sqrt(fmax(vx, 0.0) / (N * (N - 1.0)));
-            se[2 * g + 1] = sqrt(fmax(vy, 0.0) / (N * (N - 1.0)));
+            const double vx = T[2] - Nd * mx * mx, vy = T[3] - Nd * my * my;
+            se[2 * g] = sqrt(fmax(vx, 0.0) / (Nd * (Nd - 1.0)));
+            se[2 * g + 1] = sqrt(fmax(vy, 0.0) / (Nd * (Nd - 1.0)));
         } else {
             se[2 * g] = 0.0;
             se[2 * g + 1] = 0.0;
@@ -261,10 +328,10 @@ __global__ void finalize_kernel(const Slot* __restrict__ slots, int64_t n_nodes,
     }
     if (sums) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) sums[4 * g + q] = tot[q];
+        for (int q = 0; q < 4; ++q) sums[4 * g + q] = T[q];
     }
-    node_tot[2 * g] = st;
-    node_tot[2 * g + 1] = cp;
+    node_tot[2 * g] = ST;
+    node_tot[2 * g + 1] = CP;
 }
 
 // Single workgroup: totals over nodes (integer sums, order-free).
@@ -299,20 +366,67 @@ __global__ __launch_bounds__(1024) void stats_kernel(const long long* __restrict
     }
 }
 
+template <typename R, int KIND>
+static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
+{
+    // a persistent grid of 4 waves per SIMD (SDD_WALK_WAVES_PER_SIMD
+    // overrides; capped by what the device keeps resident), never more than
+    // there are tickets.  More waves hide latency better but split the paths
+    // over more lanes, and the last, longest paths then leave more lanes
+    // idle; 4 measured best on the ring workload (2..8 swept).
+    static int per_cu_blocks = -1;
+    static int cus = 0;
+    if (per_cu_blocks < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, walk_kernel<R, KIND>, kWalkBlock, 0) != hipSuccess ||
+            occ <= 0)
+            occ = 2;
+        int want = 4;  // blocks of 4 waves: one wave per SIMD each
+        const char* env = getenv("SDD_WALK_WAVES_PER_SIMD");
+        if (env && atoi(env) > 0) want = atoi(env);
+        occ = want < occ ? want : occ;
+        per_cu_blocks = occ;
+    }
+    const int64_t need = ((int64_t)A.total + kWave - 1) / kWave;
+    int64_t blocks = (int64_t)per_cu_blocks * cus;
+    const int64_t most = (need + kWalkBlock / kWave - 1) / (kWalkBlock / kWave);
+    if (blocks > most) blocks = most;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((walk_kernel<R, KIND>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, stream, A);
+    return hipGetLastError();
+}
+
+template <typename R>
+static hipError_t launch_walk_prec(const WalkArgs& A, hipStream_t stream)
+{
+    const int kind = A.dens.n_terms == 1 ? A.dens.kind[0] : kAnyTerms;
+    switch (kind) {
+    case SDD_TERM_GAUSS: return launch_walk_kernel<R, SDD_TERM_GAUSS>(A, stream);
+    case SDD_TERM_RING: return launch_walk_kernel<R, SDD_TERM_RING>(A, stream);
+    case SDD_TERM_SECH2: return launch_walk_kernel<R, SDD_TERM_SECH2>(A, stream);
+    case SDD_TERM_SIN2: return launch_walk_kernel<R, SDD_TERM_SIN2>(A, stream);
+    default: return launch_walk_kernel<R, kAnyTerms>(A, stream);
+    }
+}
+
 hipError_t launch_walk(const WalkArgs& A, int prec, double* mean, double* se, double* sums, sdd_walk_stats* stats,
                        long long* node_tot, hipStream_t stream)
 {
-    const int waves_per_block = 4;
-    const int64_t blocks = (A.n_items + waves_per_block - 1) / waves_per_block;
-    if (prec == SDD_FP32)
-        hipLaunchKernelGGL(walk_kernel<float>, dim3((unsigned)blocks), dim3(kWave * waves_per_block), 0, stream, A);
-    else
-        hipLaunchKernelGGL(walk_kernel<double>, dim3((unsigned)blocks), dim3(kWave * waves_per_block), 0, stream, A);
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, stream, A.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int tb = 256;
-    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((A.n_nodes + tb - 1) / tb)), dim3(tb), 0, stream, A.slots,
-                       A.n_nodes, A.n_chunks, A.paths, mean, se, sums, node_tot);
+    e = (prec == SDD_FP32) ? launch_walk_prec<float>(A, stream) : launch_walk_prec<double>(A, stream);
+    if (e != hipSuccess) return e;
+    if (prec == SDD_FP32)
+        hipLaunchKernelGGL(reduce_kernel<float>, dim3((unsigned)A.n_nodes), dim3(kReduceBlock), 0, stream, A.pq,
+                           A.info, A.paths, A.bmap, mean, se, sums, node_tot, A.per_path);
+    else
+        hipLaunchKernelGGL(reduce_kernel<double>, dim3((unsigned)A.n_nodes), dim3(kReduceBlock), 0, stream, A.pq,
+                           A.info, A.paths, A.bmap, mean, se, sums, node_tot, A.per_path);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (stats) {

@@ -110,7 +110,7 @@ def test_subdomain_solve_matches_direct_solve(ctx, ref, L):
     say(f"subdomain_solve {L}")
     tv = torch.as_tensor(vert).cuda() if sx > 1 else None
     th = torch.as_tensor(horiz).cuda() if sy > 1 else None
-    sol = sdd.sdd_subdomain_solve(ctx, d, bm, L, tv, th, tol=1e-14)
+    sol = sdd.sdd_subdomain_solve(ctx, d, bm, L, tv, th, tol=1e-13)
     mesh = sol["mesh"].cpu().numpy()
     sweeps = sol["sweeps"].cpu().numpy()
     resid = sol["resid"].cpu().numpy()
@@ -118,7 +118,8 @@ def test_subdomain_solve_matches_direct_solve(ctx, ref, L):
     r = ref.subdomain_solve(d, B, L, vert, horiz)
     err = np.max(np.abs(mesh - r))
     say(f"max |GPU - direct| = {err:.3e}")
-    assert np.all(resid <= 1e-14)
+    assert np.all(resid <= 1e-13)
+    assert np.all(sweeps < 20000)
     assert err <= 1e-10
     # boundary values: device and host sin/cos may differ by an ulp
     assert np.max(np.abs(mesh[0] - r[0])) <= 4e-16 and np.max(np.abs(mesh[:, 0] - r[:, 0])) <= 4e-16

@@ -49,11 +49,13 @@ def test_philox_matches_rocrand_engine(ref, tmp_path):
 
 
 def test_uniforms_exact_in_float_and_open_interval(ref):
-    w = np.array([0, 1, 511, 512, 2**31, 2**32 - 1, 2**32 - 512, 12345678], dtype=np.uint32)
+    # the low 23 bits of the word select one of 2^23 equally spaced points
+    w = np.array([0, 1, 2**23, 2**23 + 1, 2**31, 2**32 - 1, 2**23 - 1, 12345678], dtype=np.uint32)
     u = ref.uniforms(w)
-    assert u[0] == 2.0**-24 and u[1] == 2.0**-24 and u[2] == 2.0**-24
-    assert u[3] == 3 * 2.0**-24
-    assert u[5] == 1.0 - 2.0**-24
+    assert u[0] == 2.0**-24 and u[2] == 2.0**-24 and u[4] == 2.0**-24
+    assert u[1] == 3 * 2.0**-24 and u[3] == 3 * 2.0**-24
+    assert u[5] == 1.0 - 2.0**-24 and u[6] == 1.0 - 2.0**-24
+    assert u[7] == ((12345678 % 2**23) + 0.5) * 2.0**-23
     rng = np.random.default_rng(3)
     words = rng.integers(0, 2**32, size=200000, dtype=np.uint64).astype(np.uint32)
     uu = ref.uniforms(words)
@@ -83,8 +85,8 @@ def test_normals_are_standard_normal(ref):
 
 def test_box_muller_special_angles(ref):
     # u_b = 1/4 + 2^-24 is close to a quarter turn: z0 ~ 0, z1 ~ radius
-    ra = np.uint32(0x80000000)      # u_a = (2^22 + 1/2) 2^-23
-    rb = np.uint32(0x40000000)      # u_b = (2^21 + 1/2) 2^-23
+    ra = np.uint32(0x00400000)      # u_a = (2^22 + 1/2) 2^-23
+    rb = np.uint32(0x00200000)      # u_b = (2^21 + 1/2) 2^-23
     z = ref.normals64(np.array([[ra, rb]], dtype=np.uint32))[0]
     ua = (2**22 + 0.5) * 2.0**-23
     ub = (2**21 + 0.5) * 2.0**-23
