@@ -23,13 +23,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU issue model of one float Euler-Maruyama step with the ring density
-# (lane-slots; an op of the transcendental unit or a 32x32-bit integer
-# multiply occupies 4 slots, every other VALU op 1).  Derivation in the
-# design notes; the peak is 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-SLOTS_PER_STEP = {"ring": 115, "gauss": 98, "sech2": 108, "sin2": 106}
-VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3 T lane-slots/s
-FP32_FLOPS_PER_STEP = {"ring": 38, "gauss": 34, "sech2": 40, "sin2": 36}
+# Issue cost of one float Euler-Maruyama step, in SIMD cycles per wave64
+# step, from the algorithm's instruction mix weighted by the gfx950 issue
+# cost of each instruction class measured with csrc/valu_rates.hip (at the
+# measured shader clock; rounded): 2-operand VALU ops (add, sub, mul, max,
+# xor, compare) 2 cycles, 3-operand ops (fma, v_bitop3_b32, v_and_or_b32,
+# v_mad_u64_u32) 4 cycles, transcendentals (exp, log, sqrt, rsq, rcp, sin,
+# cos) 8 cycles; classes do not overlap.  Per step: half a Philox4x32-10
+# block (10 v_mad_u64_u32 + 10 v_bitop3_b32 = 80), two uniforms (2 and_or +
+# 2 add = 12), Box-Muller (4 transcendentals + 2 mul = 36), the drift (ring
+# 60, gauss 40, sech2 66, sin2 56), the update (4 fma = 16) and the exit
+# test (4 two-operand ops = 8).  Peak issue capacity: 256 CUs x 4 SIMDs x
+# 2.4 GHz.  The roofline fraction is the share of that capacity the
+# algorithm's instructions fill at the measured step rate.
+CYCLES_PER_WAVE_STEP = {"ring": 212, "gauss": 192, "sech2": 218, "sin2": 208}
+ISSUE_PEAK_G = 256 * 4 * 2.4e9 / 1e9  # G SIMD-cycles/s
+# FP32 floating-point operations per step (FMA = 2, transcendental = 1).
+FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 38, "sin2": 36}
+FP32_PEAK_TFLOPS = 157.3
 
 
 def kernel_source_hash() -> str:
@@ -164,9 +175,12 @@ def main():
 
     total_steps = steps_per_pass * args.steps
     value = total_steps / elapsed
-    kind = dens["terms"][0]["kind"] if dens["terms"] else "gauss"
-    slots = SLOTS_PER_STEP.get(kind, 100)
-    achieved = steps_per_pass * slots / walk_avg_s / 1e12
+    kind = dens["terms"][0]["kind"] if len(dens["terms"]) == 1 else None
+    per_step = CYCLES_PER_WAVE_STEP.get(kind) if cfg["prec"] == "fp32" else None
+    # G SIMD-cycles/s the algorithm's instructions occupy at the measured rate
+    achieved = steps_per_pass / 64 * per_step / walk_avg_s / 1e9 if per_step else None
+    tflops = (steps_per_pass * FP32_FLOPS_PER_STEP[kind] / walk_avg_s / 1e12
+              if cfg["prec"] == "fp32" and kind in FP32_FLOPS_PER_STEP else None)
     line = {
         "metric": "walk steps/s + interface nodes/s at fixed std error; serve p50/p99 latency",
         "value": value,
@@ -194,13 +208,14 @@ def main():
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
-            "peak": VALU_PEAK_TSLOTS,
-            "unit": "T VALU lane-slots/s",
-            "frac": achieved / VALU_PEAK_TSLOTS,
+            "peak": ISSUE_PEAK_G,
+            "unit": "G SIMD issue-cycles/s",
+            "frac": achieved / ISSUE_PEAK_G if achieved else None,
             "traffic": traffic_from_profile(args.workload),
-            "kernel": "walk_kernel<float>" if cfg["prec"] == "fp32" else "walk_kernel<double>",
-            "slots_per_step": slots,
-            "fp32_tflops": steps_per_pass * FP32_FLOPS_PER_STEP.get(kind, 34) / walk_avg_s / 1e12,
+            "kernel": "walk_kernel<%s,%s>" % ("float" if cfg["prec"] == "fp32" else "double", kind),
+            "cycles_per_wave_step": per_step,
+            "fp32_tflops": tflops,
+            "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,
         },
     }
     if not args.no_cpu_baseline:
