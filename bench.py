@@ -11,7 +11,13 @@ interior interface node estimated (1521 nodes), 1e4 paths per node,
 dt = 1e-5, float walk with compensated double accumulation.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--no-cpu-baseline]
+                    [--no-cpu-baseline] [--no-fp64] [--serve-requests N]
+                    [--serve-load RHO]
+
+Beside the throughput line it reports the double-precision walk on the same
+workload (equal paths, hence equal standard error) and a serving run: a
+Poisson stream of mesh requests at RHO x the measured capacity, with p50/p99
+latency from arrival to the mesh in host memory.
 """
 import argparse
 import hashlib
@@ -45,7 +51,7 @@ FP32_PEAK_TFLOPS = 157.3
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("walk.hip", "common.h", "kernels.h"):
+    for f in ("walk.hip", "common.h", "kernels.h", "rng.h"):
         with open(os.path.join(ROOT, "paper_1310_3435_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -94,6 +100,60 @@ def cpu_baseline(cfg, nodes, sample_nodes: int):
             "nodes_per_s": sample_nodes / el}
 
 
+def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4):
+    """Config-4 style serving: a burst of `burst` requests measures capacity
+    (requests/s at saturation); then `n_requests` arrive as a Poisson stream
+    at `load` x capacity.  Latency = arrival (submit) to the mesh being in
+    host memory, on the server's clock."""
+    import numpy as np
+
+    import paper_1310_3435_amd as sdd
+    import workloads
+
+    reqs = workloads.serving_requests(n_requests + burst, master_seed=seed)
+    srv = sdd.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=64, max_nodes=4096, max_points=257 * 257)
+    try:
+        t0 = srv.clock()
+        ids = [srv.submit(r) for r in reqs[:burst]]
+        res = [srv.wait(i) for i in ids]
+        t_burst = max(r["t_done"] for r in res) - t0
+        capacity = burst / t_burst
+        rate = load * capacity
+        arrivals = workloads.poisson_arrivals(n_requests, rate, seed=seed)
+        out, pending = [], {}
+        start = time.perf_counter()
+        for req, ta in zip(reqs[burst:], arrivals):
+            while True:
+                now = time.perf_counter() - start
+                for rid in list(pending):
+                    r = srv.poll(rid)
+                    if r is not None:
+                        out.append(r)
+                        del pending[rid]
+                if now >= ta:
+                    break
+                time.sleep(min(ta - now, 0.002))
+            pending[srv.submit(req)] = True
+        for rid in list(pending):
+            out.append(srv.wait(rid))
+        wall = max(r["t_done"] for r in out) - min(r["t_submit"] for r in out)
+    finally:
+        srv.close()
+    ok = [r for r in out if r["status"] == 0]
+    lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
+    steps = sum(r["steps"] for r in ok)
+    return {
+        "requests": len(out), "completed": len(ok), "load": load,
+        "arrival_rate_per_s": rate, "capacity_req_per_s": capacity,
+        "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+        "mean_latency_ms": float(lat.mean()), "throughput_req_per_s": len(ok) / wall,
+        "walk_steps_per_s": steps / wall, "median_paths_per_node": float(np.median([r["paths_per_node"] for r in ok])),
+        "max_se": float(max(r["max_se"] for r in ok)),
+        "stream": "1-4 Gaussian bumps (amp U[1,20], width U[20,200]), grids {33,65,129,257}^2, 2x2..8x8 "
+                  "subdomains, SE 1e-3 per node, dt 1e-4, float walks, Poisson arrivals",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +163,10 @@ def main():
     ap.add_argument("--prec", default=None, help="override the workload's walk precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nodes", type=int, default=64)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision comparison walk")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / measured capacity")
+    ap.add_argument("--serve-burst", type=int, default=16, help="requests of the capacity burst")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +282,25 @@ def main():
             "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,
         },
     }
+    if not args.no_fp64 and cfg["prec"] == "fp32":
+        # the same workload with the double-precision walk: same paths, same
+        # uniforms, hence the same standard error
+        e64 = sdd.sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp64")
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        e64 = sdd.sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp64", out=e64)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms64 = a.elapsed_time(b)
+        st64 = int(e64["stats"].cpu().numpy()[0])
+        se64 = float(np.median(e64["se"].cpu().numpy()))
+        line["fp64_walk"] = {"walk_ms": ms64, "walk_steps_per_s": st64 / (ms64 / 1e3), "median_se": se64,
+                             "fp32_speedup_at_equal_se": ms64 / float(np.mean(walk_ms)),
+                             "max_node_diff_fp32_vs_fp64": float(np.abs(e64["mean"].cpu().numpy() -
+                                                                        est["mean"].cpu().numpy()).max())}
+    if args.serve_requests > 0:
+        line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes)
     print(json.dumps(line), flush=True)

@@ -51,6 +51,8 @@ typedef enum {
     SDD_EINVAL = -1,       /* an argument is out of range or inconsistent */
     SDD_ENOSPC = -2,       /* the workspace is smaller than required */
     SDD_EDEVICE = -3,      /* a HIP runtime call failed */
+    SDD_EAGAIN = -4,       /* not finished yet (server poll) */
+    SDD_ECANCELED = -5,    /* cancelled, or the server shut down first */
     SDD_EUNSUPPORTED = -6  /* valid request this build does not implement */
 } sdd_status;
 
@@ -241,6 +243,88 @@ sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bma
                                const double* vert, const double* horiz, double tol, int32_t max_sweeps,
                                double* mesh, int32_t* sweeps, double* resid, void* workspace, size_t ws_bytes,
                                void* stream);
+
+/* -------------------------------------------------------------- serving ---
+ * A request server that batches whole mesh requests (interface estimate,
+ * fill and subdomain solves) continuously: requests that arrive while
+ * others run are admitted as slots and device memory free up, and every
+ * walk launch mixes blocks of paths from all admitted requests.
+ *
+ * Paths are walked in blocks of 1024 per node.  With se_target > 0 the
+ * first block is a pilot; the request then runs
+ * N = max(1024, ceil((s / se_target)^2)) paths per node, rounded up to a
+ * multiple of 1024, where s is the largest sample standard deviation of x
+ * or y over its nodes (the paper notes the mean's additivity makes such a
+ * stopping rule compatible with the method, Sec. 6).  With se_target <= 0
+ * paths_per_node is used, rounded up to a multiple of 1024.  Block b of a
+ * request is always reduced before block b+1, and a path's random numbers
+ * depend only on (seed, node, path, step), so a request's result is
+ * bitwise the same alone or in any mix.
+ *
+ * Requests walk in float (compensated double sums, double exit
+ * projection); the density must be a sum of up to four GAUSS terms; the
+ * boundary map IDENTITY, AFFINE or ANNULUS.  A request's device footprint
+ * (nodes, sums, interface lines, mesh, subdomain workspace) comes from an
+ * arena of hbm_budget_bytes allocated once at creation; a request is
+ * admitted first come, first served when a slot and enough arena are free.
+ * The server also holds two path-record buffers of launch_paths x 20 bytes
+ * and pinned host staging of max_slots x (max_nodes x 80 + max_points x 16)
+ * bytes.  A scheduler thread owns the device work; every call below is
+ * thread-safe.  Times are seconds on the server's steady clock. */
+typedef struct {
+    sdd_density w;
+    sdd_bmap bmap;
+    sdd_layout layout;
+    int32_t k;          /* interface points per segment */
+    int32_t placement;  /* 0 uniform, 1 equidistributed */
+    int32_t interp;     /* 0 linear, 1 monotone cubic */
+    int32_t pad;
+    double dt;
+    double se_target;       /* > 0: paths from a pilot; <= 0: paths_per_node */
+    int64_t paths_per_node; /* used when se_target <= 0 */
+    uint64_t seed;
+    double t_max;           /* step cap in time units; <= 0 selects 8 */
+} sdd_request;
+
+typedef struct {
+    int32_t status; /* SDD_OK, SDD_ECANCELED or an error */
+    int32_t pad;
+    int64_t n_nodes, paths_per_node, steps;
+    double max_se;  /* largest node standard error over both components */
+    double t_submit, t_admit, t_done; /* t_done: the mesh is in the caller's buffer */
+} sdd_result;
+
+typedef struct sdd_server sdd_server;
+
+/* max_slots requests in flight at once (1..256); requests of up to max_nodes
+ * interface points and max_points mesh nodes (nx * ny); launch_paths paths
+ * per walk launch (0 selects 2^25).  SDD_EINVAL on bad limits, SDD_EDEVICE
+ * when the device or pinned memory cannot be allocated. */
+sdd_status sdd_server_create(sdd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_slots, int64_t max_nodes,
+                             int64_t max_points, int64_t launch_paths, sdd_server** out);
+
+/* Queue a request (copied); never blocks on device work.  mesh: host
+ * [ny][nx][2], caller-owned, written before the request reports done.
+ * SDD_EINVAL for an invalid or oversized request, SDD_EUNSUPPORTED for a
+ * density or map kind the server does not walk. */
+sdd_status sdd_server_submit(sdd_server* srv, const sdd_request* req, double* mesh, uint64_t* id);
+
+/* SDD_EAGAIN until the request is done; then fills *out and returns its
+ * status (the id is released).  SDD_EINVAL for an unknown id. */
+sdd_status sdd_server_poll(sdd_server* srv, uint64_t id, sdd_result* out);
+
+/* As poll, but blocks until the request is done. */
+sdd_status sdd_server_wait(sdd_server* srv, uint64_t id, sdd_result* out);
+
+/* Cancel a queued or running request: it finishes with SDD_ECANCELED
+ * once its in-flight blocks have drained, its mesh untouched. */
+sdd_status sdd_server_cancel(sdd_server* srv, uint64_t id);
+
+/* Seconds on the server's clock (the clock of sdd_result). */
+double sdd_server_clock(sdd_server* srv);
+
+/* Cancel everything pending, drain the device, free all memory. */
+sdd_status sdd_server_destroy(sdd_server* srv);
 
 #ifdef __cplusplus
 }

@@ -56,6 +56,21 @@ class sdd_walk_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("paths", C.c_int64), ("capped", C.c_int64)]
 
 
+class sdd_request(C.Structure):
+    _fields_ = [("w", sdd_density), ("bmap", sdd_bmap), ("layout", sdd_layout), ("k", C.c_int32),
+                ("placement", C.c_int32), ("interp", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
+                ("se_target", C.c_double), ("paths_per_node", C.c_int64), ("seed", C.c_uint64),
+                ("t_max", C.c_double)]
+
+
+class sdd_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("pad", C.c_int32), ("n_nodes", C.c_int64), ("paths_per_node", C.c_int64),
+                ("steps", C.c_int64), ("max_se", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+SDD_EINVAL, SDD_EAGAIN, SDD_ECANCELED, SDD_EUNSUPPORTED = -1, -4, -5, -6
+
 PATH_RECORD = np.dtype([("exit_xi", "<f8"), ("exit_eta", "<f8"), ("steps", "<i8"), ("side", "<i4"),
                         ("capped", "<i4")])
 
@@ -96,13 +111,29 @@ def lib() -> C.CDLL:
     L.sdd_subdomain_solve.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), C.POINTER(sdd_layout), P, P,
                                       D, I32, P, P, P, P, SZ, P]
     L.sdd_subdomain_solve.restype = C.c_int
+    L.sdd_server_create.argtypes = [P, SZ, I32, I64, I64, I64, C.POINTER(P)]
+    L.sdd_server_create.restype = C.c_int
+    L.sdd_server_submit.argtypes = [P, C.POINTER(sdd_request), P, C.POINTER(C.c_uint64)]
+    L.sdd_server_submit.restype = C.c_int
+    L.sdd_server_poll.argtypes = [P, C.c_uint64, C.POINTER(sdd_result)]
+    L.sdd_server_poll.restype = C.c_int
+    L.sdd_server_wait.argtypes = [P, C.c_uint64, C.POINTER(sdd_result)]
+    L.sdd_server_wait.restype = C.c_int
+    L.sdd_server_cancel.argtypes = [P, C.c_uint64]
+    L.sdd_server_cancel.restype = C.c_int
+    L.sdd_server_clock.argtypes = [P]
+    L.sdd_server_clock.restype = D
+    L.sdd_server_destroy.argtypes = [P]
+    L.sdd_server_destroy.restype = C.c_int
     _lib = L
     return L
 
 
 EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd_workspace_bytes",
            "sdd_interface_estimate", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
-           "sdd_fill_interfaces", "sdd_subdomain_workspace_bytes", "sdd_subdomain_solve"]
+           "sdd_fill_interfaces", "sdd_subdomain_workspace_bytes", "sdd_subdomain_solve", "sdd_server_create",
+           "sdd_server_submit", "sdd_server_poll", "sdd_server_wait", "sdd_server_cancel", "sdd_server_clock",
+           "sdd_server_destroy"]
 
 
 def _check(rc: int, what: str):
@@ -356,3 +387,88 @@ def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -
     sol = sdd_subdomain_solve(ctx, dens, B, L, vert, horiz, stream=stream)
     return {"nodes": nodes, "est": est, "vert": vert, "horiz": horiz, "mesh": sol["mesh"], "sweeps": sol["sweeps"],
             "resid": sol["resid"], "_keep": (B, sol)}
+
+
+# ------------------------------------------------------------ serving
+
+def make_request(req: dict) -> sdd_request:
+    """sdd_request from a dict with the keys of workloads.serving_requests()."""
+    R = sdd_request()
+    R.w = make_density(req["density"])
+    b = req["bmap"]
+    R.bmap.kind = BMAP[b["kind"]]
+    for i, v in enumerate(b.get("p", [])):
+        R.bmap.p[i] = float(v)
+    R.layout = make_layout(req["layout"])
+    R.k = int(req["k"])
+    R.placement = PLACEMENT[req.get("placement", "uniform")]
+    R.interp = INTERP[req.get("interp", "linear")]
+    R.dt = float(req["dt"])
+    R.se_target = float(req.get("se_target", 0.0))
+    R.paths_per_node = int(req.get("paths", 0))
+    R.seed = int(req["seed"]) & 0xFFFFFFFFFFFFFFFF
+    R.t_max = float(req.get("t_max", 0.0))
+    return R
+
+
+class Server:
+    """Request server of the C ABI (sdd_server_*): continuous batching of
+    whole mesh requests on the device.  Meshes land in host numpy arrays."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 1 << 30, max_slots: int = 64,
+                 max_nodes: int = 8192, max_points: int = 257 * 257, launch_paths: int = 0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(lib().sdd_server_create(ctx.h, int(hbm_budget_bytes), int(max_slots), int(max_nodes),
+                                       int(max_points), int(launch_paths), C.byref(h)), "sdd_server_create")
+        self.h = h
+        self.meshes = {}
+
+    def submit(self, req: dict) -> int:
+        R = make_request(req)
+        L = req["layout"]
+        mesh = np.zeros((L["ny"], L["nx"], 2))
+        rid = C.c_uint64()
+        _check(lib().sdd_server_submit(self.h, C.byref(R), mesh.ctypes.data_as(C.c_void_p), C.byref(rid)),
+               "sdd_server_submit")
+        self.meshes[rid.value] = mesh
+        return rid.value
+
+    def _result(self, rc, res, rid):
+        out = {"status": rc, "n_nodes": res.n_nodes, "paths_per_node": res.paths_per_node, "steps": res.steps,
+               "max_se": res.max_se, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
+               "mesh": self.meshes.pop(rid, None)}
+        return out
+
+    def poll(self, rid: int):
+        res = sdd_result()
+        rc = lib().sdd_server_poll(self.h, rid, C.byref(res))
+        if rc == SDD_EAGAIN:
+            return None
+        if rc == SDD_EINVAL:
+            raise SddError("unknown request id")
+        return self._result(rc, res, rid)
+
+    def wait(self, rid: int):
+        res = sdd_result()
+        rc = lib().sdd_server_wait(self.h, rid, C.byref(res))
+        if rc == SDD_EINVAL:
+            raise SddError("unknown request id")
+        return self._result(rc, res, rid)
+
+    def cancel(self, rid: int):
+        _check(lib().sdd_server_cancel(self.h, rid), "sdd_server_cancel")
+
+    def clock(self) -> float:
+        return float(lib().sdd_server_clock(self.h))
+
+    def close(self):
+        if self.h:
+            _check(lib().sdd_server_destroy(self.h), "sdd_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

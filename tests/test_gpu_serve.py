@@ -1,0 +1,137 @@
+"""GPU tests of the request server (continuous batching).
+
+* a request's mesh is bitwise the same alone and in a mix of other requests
+  (paths depend only on their counters; blocks reduce in a fixed order);
+* a served request agrees with the oracle's pipeline under common random
+  numbers (within 3 standard errors of the double-precision walk);
+* admission by device memory: a budget that holds one request runs the
+  stream one at a time, first come first served;
+* cancellation and shutdown with work in flight end cleanly.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1310_3435_amd as sdd
+    return sdd.Context(0)
+
+
+def small_request(seed=77, n=33, s=2, paths=0, se=1e-3, bumps=None):
+    terms = bumps or [{"kind": "gauss", "amp": 6.0, "coef": 60.0, "cx": 0.4, "cy": 0.55}]
+    return {"density": W.density(1.0, terms), "bmap": {"kind": "identity"},
+            "layout": {"nx": n, "ny": n, "sx": s, "sy": s}, "k": (n - 1) // s - 1, "placement": "uniform",
+            "interp": "linear", "dt": 1e-4, "se_target": se, "paths": paths, "seed": seed}
+
+
+def test_result_is_the_same_alone_and_in_a_mix(ctx):
+    import paper_1310_3435_amd as sdd
+    target = small_request()
+    srv = sdd.Server(ctx, hbm_budget_bytes=256 << 20, max_slots=16)
+    try:
+        say("serve: target alone")
+        alone = srv.wait(srv.submit(target))
+        assert alone["status"] == 0
+        mix = W.serving_requests(24, master_seed=9, grids=(33, 65), splits=(2, 4))
+        ids = [srv.submit(r) for r in mix[:12]]
+        tid = srv.submit(target)
+        ids += [srv.submit(r) for r in mix[12:]]
+        say(f"serve: target in a mix of {len(mix)}")
+        res = [srv.wait(i) for i in ids]
+        mixed = srv.wait(tid)
+    finally:
+        srv.close()
+    assert mixed["status"] == 0 and all(r["status"] == 0 for r in res)
+    assert mixed["paths_per_node"] == alone["paths_per_node"] >= 1024
+    assert mixed["steps"] == alone["steps"]
+    assert np.array_equal(mixed["mesh"], alone["mesh"])
+    say(f"paths/node {alone['paths_per_node']}, max SE {alone['max_se']:.2e}, bitwise equal")
+    # the requested standard error was met
+    assert alone["max_se"] <= 1e-3 * 1.05
+    for r in res:
+        assert np.all(np.isfinite(r["mesh"])) and r["max_se"] <= 1e-3 * 1.05
+
+
+def test_served_mesh_matches_the_oracle_pipeline(ctx, ref):
+    import paper_1310_3435_amd as sdd
+    req = small_request(seed=5, paths=2048, se=0.0,
+                        bumps=[{"kind": "gauss", "amp": 6.0, "coef": 60.0, "cx": 0.4, "cy": 0.55},
+                               {"kind": "gauss", "amp": 3.0, "coef": 150.0, "cx": 0.7, "cy": 0.3}])
+    srv = sdd.Server(ctx, hbm_budget_bytes=64 << 20, max_slots=4)
+    try:
+        say("serve: parity request")
+        out = srv.wait(srv.submit(req))
+    finally:
+        srv.close()
+    assert out["status"] == 0 and out["paths_per_node"] == 2048
+    cfg = dict(req, paths=2048, prec="fp64")
+    r64 = ref.pipeline(cfg)
+    se = r64["est"]["se"].max()
+    diff = np.abs(out["mesh"] - r64["mesh"]).max()
+    say(f"served vs oracle double pipeline: max |diff| {diff:.3e}, node SE <= {se:.3e}")
+    assert diff <= 3 * se
+    r32 = ref.pipeline(dict(cfg, prec="fp32"))
+    d32 = np.abs(out["mesh"] - r32["mesh"]).max()
+    say(f"served vs oracle float pipeline: max |diff| {d32:.3e}")
+    assert d32 <= 0.5 * se
+
+
+def test_admission_by_device_memory_is_first_come_first_served(ctx):
+    import paper_1310_3435_amd as sdd
+    reqs = [small_request(seed=100 + i, n=65, s=4, paths=1024, se=0.0) for i in range(4)]
+    # one 65^2 request with 4x4 subdomains needs ~187 KB of arena: 250 KB holds one
+    srv = sdd.Server(ctx, hbm_budget_bytes=250 << 10, max_slots=8)
+    try:
+        say("serve: tiny arena, 4 requests")
+        ids = [srv.submit(r) for r in reqs]
+        res = [srv.wait(i) for i in ids]
+    finally:
+        srv.close()
+    assert all(r["status"] == 0 for r in res)
+    for a, b in zip(res, res[1:]):
+        assert b["t_admit"] >= a["t_done"] - 1e-3   # admitted only after the previous one freed its memory
+    assert all(np.all(np.isfinite(r["mesh"])) for r in res)
+
+
+def test_cancel_and_shutdown(ctx):
+    import paper_1310_3435_amd as sdd
+    srv = sdd.Server(ctx, hbm_budget_bytes=250 << 10, max_slots=2)
+    big = small_request(seed=3, n=65, s=4, se=2e-4)
+    a = srv.submit(big)
+    b = srv.submit(small_request(seed=4, n=65, s=4, se=2e-4))   # queued behind a (arena)
+    srv.cancel(b)
+    rb = srv.wait(b)
+    assert rb["status"] == sdd.SDD_ECANCELED and np.all(rb["mesh"] == 0)
+    srv.cancel(a)
+    ra = srv.wait(a)
+    assert ra["status"] == sdd.SDD_ECANCELED
+    # shutdown with requests still running drains and returns
+    for i in range(3):
+        srv.submit(small_request(seed=10 + i, n=65, s=4, se=2e-4))
+    say("serve: destroy with work in flight")
+    srv.close()
+
+
+def test_rejected_requests(ctx):
+    import paper_1310_3435_amd as sdd
+    srv = sdd.Server(ctx, hbm_budget_bytes=8 << 20, max_slots=2, max_nodes=100, max_points=65 * 65)
+    try:
+        ring = small_request()
+        ring["density"] = W.density(1.0, [{"kind": "ring", "amp": 1.0, "coef": 10.0, "cx": 0.5, "cy": 0.5,
+                                          "r0": 0.2}])
+        with pytest.raises(sdd.SddError, match="unsupported"):
+            srv.submit(ring)
+        with pytest.raises(sdd.SddError, match="invalid"):
+            srv.submit(small_request(n=129, s=2))     # more points than max_points
+        with pytest.raises(sdd.SddError, match="invalid"):
+            srv.submit(dict(small_request(), dt=0.0))
+        ok = srv.wait(srv.submit(small_request(paths=1024, se=0.0)))
+        assert ok["status"] == 0
+    finally:
+        srv.close()
