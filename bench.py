@@ -154,6 +154,60 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4):
     }
 
 
+def closed_form_sin2(xi):
+    """x(xi) = int_0^xi 1/w / int_0^1 1/w for w = 1 + 3 sin^2(2 pi xi): with
+    Theta(t) = arctan(2 tan t) continued through the poles, x = Theta(2 pi xi)/(2 pi)."""
+    import numpy as np
+    t = 2 * np.pi * np.asarray(xi, dtype=np.float64)
+    th = np.arctan2(2 * np.sin(t), np.cos(t))
+    return np.where(th < 0, th + 2 * np.pi, th) / (2 * np.pi)
+
+
+def bias_sweep(paths: int, dts):
+    """Float and double walks on the closed-form workload at every dt: time,
+    steps/s and the error of the node estimates against the exact solution
+    (x = closed form, y = 1/2)."""
+    import numpy as np
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    import workloads
+
+    cfg = workloads.cfg_sin2_sweep()
+    ctx = sdd.Context(0)
+    dens = cfg["density"]
+    B = sdd.Bmap(cfg["bmap"], ctx, dens)
+    nodes_np = np.array(cfg["nodes"])
+    nodes = torch.as_tensor(nodes_np).cuda()
+    exact = np.stack([closed_form_sin2(nodes_np[:, 0]), np.full(len(nodes_np), 0.5)], 1)
+    rows = []
+    for dt in dts:
+        res = {}
+        for prec in ("fp32", "fp64"):
+            stream = torch.cuda.current_stream()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            o = sdd.sdd_interface_estimate(ctx, dens, B, nodes, paths, dt, cfg["seed"], prec)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            m, se = o["mean"].cpu().numpy(), o["se"].cpu().numpy()
+            steps = int(o["stats"].cpu().numpy()[0])
+            err = m - exact
+            res[prec] = m
+            rows.append({"dt": dt, "walk": prec, "ms": ms, "steps_per_s": steps / (ms / 1e3),
+                         "mean_steps_per_path": steps / (paths * len(nodes_np)),
+                         "max_abs_err_x": float(np.abs(err[:, 0]).max()),
+                         "mean_err_x": float(err[:, 0].mean()),
+                         "max_abs_err_y": float(np.abs(err[:, 1]).max()),
+                         "median_se": float(np.median(se)),
+                         "max_err_over_se": float(np.abs(err / se).max())})
+        rows[-1]["max_diff_fp32_fp64"] = float(np.abs(res["fp32"] - res["fp64"]).max())
+        print(json.dumps(rows[-2]), flush=True)
+        print(json.dumps(rows[-1]), flush=True)
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +221,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / measured capacity")
     ap.add_argument("--serve-burst", type=int, default=16, help="requests of the capacity burst")
+    ap.add_argument("--bias-sweep", action="store_true",
+                    help="only run the float/double dt sweep of the closed-form workload")
+    ap.add_argument("--sweep-paths", type=int, default=1000000)
+    ap.add_argument("--sweep-dts", default="1e-3,1e-4,1e-5,1e-6")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -180,6 +238,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4}), flush=True)
+        return
+
+    if args.bias_sweep:
+        rows = bias_sweep(args.sweep_paths, [float(v) for v in args.sweep_dts.split(",")])
+        print(json.dumps({"bias_sweep": rows, "paths_per_node": args.sweep_paths, "nodes": 64,
+                          "workload": "sin2_bias_sweep"}), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
