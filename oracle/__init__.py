@@ -95,9 +95,12 @@ def lib():
         L.sddref_bmap_eval.argtypes = [C.POINTER(RefBmap), C.c_int64, P, P, P]
         L.sddref_exit_point.argtypes = [C.c_double] * 4 + [P, P]
         L.sddref_exit_point.restype = C.c_int
+        L.sddref_bridge_uniforms.argtypes = [C.c_int64, P, P]
+        L.sddref_bridge_exit_prob.argtypes = [C.c_double] * 5 + [P]
+        L.sddref_bridge_exit_prob.restype = C.c_double
         L.sddref_interface_estimate.argtypes = [
             C.POINTER(RefDensity), C.POINTER(RefBmap), P, P, C.c_int64, C.c_int64, C.c_int64,
-            C.c_double, C.c_uint64, C.c_int, C.c_double, C.c_int, P, P, P, P, P, C.c_int]
+            C.c_double, C.c_uint64, C.c_int, C.c_double, C.c_int, C.c_int, P, P, P, P, P, C.c_int]
         L.sddref_interface_estimate.restype = C.c_int
         _lib = L
     return _lib
@@ -205,12 +208,34 @@ def exit_point(p, q):
     return side, (ex.value, ey.value)
 
 
+def bridge_uniforms(words: np.ndarray) -> np.ndarray:
+    """Uniforms of the bridge test from word pairs [n][2] (the nine high bits
+    of each word)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 2)
+    u = np.empty(words.shape[0], dtype=np.float64)
+    lib().sddref_bridge_uniforms(words.shape[0], _ptr(words), _ptr(u))
+    return u
+
+
+def bridge_exit_prob(p, q, dt: float):
+    """Brownian-bridge exit probability of the step p -> q (both inside the
+    square) and the side it exits through (Sec. 2.2)."""
+    side = C.c_int()
+    prob = lib().sddref_bridge_exit_prob(float(p[0]), float(p[1]), float(q[0]), float(q[1]), float(dt),
+                                         C.byref(side))
+    return prob, side.value
+
+
 # ------------------------------------------------------------------ estimate
 
 def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: float, seed: int,
                        prec: str = "fp64", t_max: float = 8.0, node_ids=None, path_begin: int = 0,
-                       per_path: bool = False, proj_mode: int = 0, nthreads: int = 0) -> dict:
+                       per_path: bool = False, proj_mode: int = 0, nthreads: int = 0,
+                       bridge: bool = False) -> dict:
     """Monte Carlo estimate of (x, y) at every node (eq. (7a), Sec. 2.2).
+
+    bridge=True adds the Brownian-bridge exit test after every step (the
+    conditional exit probability of Sec. 2.2).
 
     Returns dict(mean[n,2], se[n,2], sums[n,4], steps, paths, capped[, per_path]).
     """
@@ -226,7 +251,7 @@ def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: f
     rec = np.zeros((n, paths), dtype=PATH_RECORD) if per_path else None
     rc = lib().sddref_interface_estimate(
         C.byref(D), C.byref(B.s), _ptr(nodes), _ptr(ids), n, int(paths), int(path_begin), float(dt),
-        C.c_uint64(int(seed)), _PREC[prec], float(t_max), int(proj_mode), _ptr(mean), _ptr(se),
+        C.c_uint64(int(seed)), _PREC[prec], float(t_max), int(proj_mode), int(bool(bridge)), _ptr(mean), _ptr(se),
         _ptr(sums), _ptr(stats), _ptr(rec), int(nthreads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -555,7 +580,7 @@ def pipeline(cfg: dict, nthreads: int = 0) -> dict:
     L = cfg["layout"]
     nodes = layout_nodes(L, cfg["k"], cfg.get("placement", "uniform"), dens)
     est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
-                             nthreads=nthreads)
+                             nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge")
     vert, horiz = fill_interfaces(L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"))
     mesh = subdomain_solve(dens, B, L, vert, horiz)
     return {"nodes": nodes, "est": est, "vert": vert, "horiz": horiz, "mesh": mesh}

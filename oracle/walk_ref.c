@@ -313,6 +313,72 @@ static int nearest_boundary(double px, double py, double* ex, double* ey)
     return side;
 }
 
+/* ------------------------------------------------------- bridge exit test */
+
+/* Uniform from the 9 high bits of each of the step's two words (18 bits):
+ * u = (b + 1/2) 2^-18 with b = (ra >> 23) | (rb >> 23) << 9.  These bits are
+ * not used by the normals, which take the low 23 bits. */
+static double bridge_uniform(uint32_t ra, uint32_t rb)
+{
+    uint32_t b = (ra >> 23) | ((rb >> 23) << 9);
+    return ((double)b + 0.5) * 0x1p-18;
+}
+
+/* Bridge uniforms of n word pairs (test access). */
+void sddref_bridge_uniforms(int64_t n, const uint32_t* words, double* u)
+{
+    for (int64_t i = 0; i < n; ++i) u[i] = bridge_uniform(words[2 * i], words[2 * i + 1]);
+}
+
+/* Brownian-bridge exit test (the conditional exit probability within a step
+ * of Sec. 2.2).  Given the step P -> Q with both ends inside, each
+ * coordinate of the Brownian bridge between them is an independent
+ * one-dimensional bridge with diffusion coefficient 2 over time dt, and such
+ * a bridge from distance a to distance b off a wall hits it with probability
+ * exp(-a b / dt).  Per axis the nearer wall is taken (the far one is at
+ * distance ~1 and contributes nothing at the time steps used); the path
+ * exits with probability 1 - (1 - p_xi)(1 - p_eta), through the side of the
+ * axis with the larger probability (xi on ties).
+ * Returns the probability; *side receives that side. */
+double sddref_bridge_exit_prob(double px, double py, double qx, double qy, double dt, int* side)
+{
+    double m0 = px * qx, m1 = (1.0 - px) * (1.0 - qx);
+    double m2 = py * qy, m3 = (1.0 - py) * (1.0 - qy);
+    double mx = (m0 <= m1) ? m0 : m1, my = (m2 <= m3) ? m2 : m3;
+    double pxi = exp(-mx / dt), peta = exp(-my / dt);
+    *side = (mx <= my) ? ((m0 <= m1) ? 0 : 1) : ((m2 <= m3) ? 2 : 3);
+    return fma(-pxi, peta, pxi + peta);
+}
+
+static float bridge_exit_prob32(float px, float py, float qx, float qy, float dt, int* side)
+{
+    float m0 = px * qx, m1 = (1.0f - px) * (1.0f - qx);
+    float m2 = py * qy, m3 = (1.0f - py) * (1.0f - qy);
+    float mx = (m0 <= m1) ? m0 : m1, my = (m2 <= m3) ? m2 : m3;
+    float pxi = expf(-mx / dt), peta = expf(-my / dt);
+    *side = (mx <= my) ? ((m0 <= m1) ? 0 : 1) : ((m2 <= m3) ? 2 : 3);
+    return fmaf(-pxi, peta, pxi + peta);
+}
+
+static int bridge_exit64(double px, double py, double qx, double qy, double dt, double u)
+{
+    int s;
+    return (u < sddref_bridge_exit_prob(px, py, qx, qy, dt, &s)) ? s : -1;
+}
+
+static int bridge_exit32(float px, float py, float qx, float qy, float dt, float u)
+{
+    int s;
+    return (u < bridge_exit_prob32(px, py, qx, qy, dt, &s)) ? s : -1;
+}
+
+/* Q projected onto side s. */
+static void onto_side(int s, double qx, double qy, double* ex, double* ey)
+{
+    *ex = (s == 0) ? 0.0 : (s == 1) ? 1.0 : qx;
+    *ey = (s == 2) ? 0.0 : (s == 3) ? 1.0 : qy;
+}
+
 /* ------------------------------------------------------------ one path */
 
 typedef struct {
@@ -325,10 +391,11 @@ typedef struct {
 
 /* proj_mode 0: value at the projected exit point (the method).
  * proj_mode 1: test mode, the map evaluated at the unprojected overshoot
- *              point X_{k+1} (only meaningful for identity/affine maps). */
+ *              point X_{k+1} (only meaningful for identity/affine maps).
+ * exit_test 1: also apply the Brownian-bridge exit test after each step. */
 static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, double eta0,
                         uint64_t g, uint64_t p, double dt, const uint32_t key[2], int64_t kmax,
-                        int proj_mode, path_out* o)
+                        int proj_mode, int bridge, path_out* o)
 {
     const double s = sqrt(2.0 * dt);
     double X = xi0, Y = eta0;
@@ -362,6 +429,15 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
             o->capped = 0;
             break;
         }
+        if (bridge) {
+            int sb = bridge_exit64(X, Y, Xn, Yn, dt, bridge_uniform(ra, rb));
+            if (sb >= 0) {
+                onto_side(sb, Xn, Yn, &o->exi, &o->eeta);
+                o->side = sb;
+                o->capped = 0;
+                break;
+            }
+        }
         X = Xn; Y = Yn;
     }
     o->steps = k;
@@ -370,7 +446,7 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
 
 static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, double eta0,
                         uint64_t g, uint64_t p, double dt, const uint32_t key[2], int64_t kmax,
-                        int proj_mode, path_out* o)
+                        int proj_mode, int bridge, path_out* o)
 {
     const float s = (float)sqrt(2.0 * dt);
     const float dtf = (float)dt;
@@ -405,6 +481,15 @@ static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, dou
             o->capped = 0;
             break;
         }
+        if (bridge) {
+            int sb = bridge_exit32(X, Y, Xn, Yn, dtf, (float)bridge_uniform(ra, rb));
+            if (sb >= 0) {
+                onto_side(sb, (double)Xn, (double)Yn, &o->exi, &o->eeta);
+                o->side = sb;
+                o->capped = 0;
+                break;
+            }
+        }
         X = Xn; Y = Yn;
     }
     o->steps = k;
@@ -432,6 +517,7 @@ static double nsum_get(const nsum* a) { return a->s + a->c; }
  * paths, path_begin paths path_begin .. path_begin+paths-1 are walked
  * mean[n][2], se[n][2]  outputs; sums[n][4] (optional) = sum x, sum y,
  *                   sum x^2, sum y^2 before division
+ * exit_test         0: end-of-step test only; 1: also the Brownian-bridge test
  * stats[3]          total steps, total paths, capped paths
  * per_path[n][paths] optional records
  * Returns 0, or -1 on invalid arguments.
@@ -439,10 +525,11 @@ static double nsum_get(const nsum* a) { return a->s + a->c; }
 int sddref_interface_estimate(const ref_density* d, const ref_bmap* b, const double* nodes,
                               const int64_t* node_ids, int64_t n, int64_t paths, int64_t path_begin,
                               double dt, uint64_t seed, int prec, double t_max, int proj_mode,
-                              double* mean, double* se, double* sums, int64_t* stats,
+                              int exit_test, double* mean, double* se, double* sums, int64_t* stats,
                               ref_path_record* per_path, int nthreads)
 {
     if (n < 1 || paths < 1 || !(dt > 0.0) || !(dt < 1.0) || path_begin < 0) return -1;
+    if (exit_test != 0 && exit_test != 1) return -1;
     for (int64_t i = 0; i < n; ++i) {
         double a = nodes[2 * i], c = nodes[2 * i + 1];
         if (!(a > 0.0 && a < 1.0 && c > 0.0 && c < 1.0)) return -1;
@@ -463,9 +550,9 @@ int sddref_interface_estimate(const ref_density* d, const ref_bmap* b, const dou
             const uint64_t p = (uint64_t)(path_begin + j);
             path_out o;
             if (prec == REF_FP32)
-                walk_path32(d, b, nodes[2 * i], nodes[2 * i + 1], g, p, dt, key, kmax, proj_mode, &o);
+                walk_path32(d, b, nodes[2 * i], nodes[2 * i + 1], g, p, dt, key, kmax, proj_mode, exit_test, &o);
             else
-                walk_path64(d, b, nodes[2 * i], nodes[2 * i + 1], g, p, dt, key, kmax, proj_mode, &o);
+                walk_path64(d, b, nodes[2 * i], nodes[2 * i + 1], g, p, dt, key, kmax, proj_mode, exit_test, &o);
             nsum_add(&sx, o.x);
             nsum_add(&sy, o.y);
             nsum_add(&sxx, o.x * o.x);
