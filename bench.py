@@ -163,10 +163,10 @@ def closed_form_sin2(xi):
     return np.where(th < 0, th + 2 * np.pi, th) / (2 * np.pi)
 
 
-def bias_sweep(paths: int, dts):
-    """Float and double walks on the closed-form workload at every dt: time,
-    steps/s and the error of the node estimates against the exact solution
-    (x = closed form, y = 1/2)."""
+def sin2_estimate(ctx, paths: int, dt: float, prec: str, exit_test: str, warm: bool = True):
+    """One timed walk of the 64-node sin^2 workload (after an untimed one of
+    1024 paths, which loads the kernel); errors against the closed form.
+    Returns a row of figures."""
     import numpy as np
     import torch
 
@@ -174,38 +174,86 @@ def bias_sweep(paths: int, dts):
     import workloads
 
     cfg = workloads.cfg_sin2_sweep()
-    ctx = sdd.Context(0)
     dens = cfg["density"]
     B = sdd.Bmap(cfg["bmap"], ctx, dens)
     nodes_np = np.array(cfg["nodes"])
     nodes = torch.as_tensor(nodes_np).cuda()
     exact = np.stack([closed_form_sin2(nodes_np[:, 0]), np.full(len(nodes_np), 0.5)], 1)
+    stream = torch.cuda.current_stream()
+    if warm:
+        sdd.sdd_interface_estimate(ctx, dens, B, nodes, min(paths, 1024), dt, cfg["seed"], prec, exit_test=exit_test)
+        torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    o = sdd.sdd_interface_estimate(ctx, dens, B, nodes, paths, dt, cfg["seed"], prec, exit_test=exit_test)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    m, se = o["mean"].cpu().numpy(), o["se"].cpu().numpy()
+    steps = int(o["stats"].cpu().numpy()[0])
+    err = m - exact
+    return {"dt": dt, "walk": prec, "exit_test": exit_test, "ms": ms, "steps_per_s": steps / (ms / 1e3),
+            "mean_steps_per_path": steps / (paths * len(nodes_np)),
+            "max_abs_err_x": float(np.abs(err[:, 0]).max()), "mean_err_x": float(err[:, 0].mean()),
+            "max_abs_err_y": float(np.abs(err[:, 1]).max()), "median_se": float(np.median(se)),
+            "max_err_over_se": float(np.abs(err / se).max()), "_mean": m}
+
+
+def bias_sweep(paths: int, dts, exit_tests=("step", "bridge")):
+    """Bias of the exit point against the closed form of the w(xi) workload,
+    float and double walks, for each time step and exit test."""
+    import numpy as np
+
+    import paper_1310_3435_amd as sdd
+    ctx = sdd.Context(0)
     rows = []
-    for dt in dts:
-        res = {}
-        for prec in ("fp32", "fp64"):
-            stream = torch.cuda.current_stream()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            o = sdd.sdd_interface_estimate(ctx, dens, B, nodes, paths, dt, cfg["seed"], prec)
-            b.record(stream)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b)
-            m, se = o["mean"].cpu().numpy(), o["se"].cpu().numpy()
-            steps = int(o["stats"].cpu().numpy()[0])
-            err = m - exact
-            res[prec] = m
-            rows.append({"dt": dt, "walk": prec, "ms": ms, "steps_per_s": steps / (ms / 1e3),
-                         "mean_steps_per_path": steps / (paths * len(nodes_np)),
-                         "max_abs_err_x": float(np.abs(err[:, 0]).max()),
-                         "mean_err_x": float(err[:, 0].mean()),
-                         "max_abs_err_y": float(np.abs(err[:, 1]).max()),
-                         "median_se": float(np.median(se)),
-                         "max_err_over_se": float(np.abs(err / se).max())})
-        rows[-1]["max_diff_fp32_fp64"] = float(np.abs(res["fp32"] - res["fp64"]).max())
-        print(json.dumps(rows[-2]), flush=True)
-        print(json.dumps(rows[-1]), flush=True)
+    for et in exit_tests:
+        for dt in dts:
+            r32 = sin2_estimate(ctx, paths, dt, "fp32", et)
+            r64 = sin2_estimate(ctx, paths, dt, "fp64", et)
+            r64["max_diff_fp32_fp64"] = float(np.abs(r32["_mean"] - r64["_mean"]).max())
+            for r in (r32, r64):
+                r.pop("_mean")
+                rows.append(r)
+                print(json.dumps(r), flush=True)
     return rows
+
+
+def bridge_legs(ctx, cfg, B, nodes, plain_walk_ms: float, plain_steps: int, plain_mean, sin2_paths: int):
+    """The Brownian-bridge exit test: its cost on the throughput workload
+    (same paths, fewer steps each) and the time to a given exit bias on the
+    closed-form workload, against the end-of-step test at a 100x smaller
+    time step."""
+    import numpy as np
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    stream = torch.cuda.current_stream()
+    o = sdd.sdd_interface_estimate(ctx, cfg["density"], B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg["prec"],
+                                   exit_test="bridge")
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    o = sdd.sdd_interface_estimate(ctx, cfg["density"], B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg["prec"],
+                                   exit_test="bridge", out=o)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    steps = int(o["stats"].cpu().numpy()[0])
+    paths = int(o["stats"].cpu().numpy()[1])
+    out = {"workload": cfg["name"], "walk_ms": ms, "walk_steps_per_s": steps / (ms / 1e3),
+           "steps_per_path": steps / paths, "plain_steps_per_path": plain_steps / paths,
+           "cost_per_step_vs_plain": (ms / steps) / (plain_walk_ms / plain_steps),
+           "max_node_shift_vs_plain": float(np.abs(o["mean"].cpu().numpy() - plain_mean).max())}
+    plain = sin2_estimate(ctx, sin2_paths, 1e-6, "fp32", "step")
+    bridge = sin2_estimate(ctx, sin2_paths, 1e-4, "fp32", "bridge")
+    for r in (plain, bridge):
+        r.pop("_mean")
+    out["equal_bias"] = {"workload": f"sin2_1d_closed_form, 64 nodes x {sin2_paths} paths, float walk",
+                         "step_dt_1e-6": plain, "bridge_dt_1e-4": bridge,
+                         "bridge_speedup": plain["ms"] / bridge["ms"],
+                         "bridge_err_ratio": bridge["max_abs_err_x"] / plain["max_abs_err_x"]}
+    return out
 
 
 def main():
@@ -225,6 +273,9 @@ def main():
                     help="only run the float/double dt sweep of the closed-form workload")
     ap.add_argument("--sweep-paths", type=int, default=1000000)
     ap.add_argument("--sweep-dts", default="1e-3,1e-4,1e-5,1e-6")
+    ap.add_argument("--sweep-exit", default="step,bridge", help="exit tests of the sweep")
+    ap.add_argument("--bridge-paths", type=int, default=1000000,
+                    help="paths per node of the equal-bias comparison (0: skip the bridge legs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -241,7 +292,8 @@ def main():
         return
 
     if args.bias_sweep:
-        rows = bias_sweep(args.sweep_paths, [float(v) for v in args.sweep_dts.split(",")])
+        rows = bias_sweep(args.sweep_paths, [float(v) for v in args.sweep_dts.split(",")],
+                          tuple(args.sweep_exit.split(",")))
         print(json.dumps({"bias_sweep": rows, "paths_per_node": args.sweep_paths, "nodes": 64,
                           "workload": "sin2_bias_sweep"}), flush=True)
         return
@@ -363,6 +415,9 @@ def main():
                              "fp32_speedup_at_equal_se": ms64 / float(np.mean(walk_ms)),
                              "max_node_diff_fp32_vs_fp64": float(np.abs(e64["mean"].cpu().numpy() -
                                                                         est["mean"].cpu().numpy()).max())}
+    if args.bridge_paths > 0:
+        line["bridge"] = bridge_legs(ctx, cfg, B, nodes, float(np.mean(walk_ms)), steps_per_pass,
+                                     est["mean"].cpu().numpy(), args.bridge_paths)
     if args.serve_requests > 0:
         line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst)
     if not args.no_cpu_baseline:

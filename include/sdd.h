@@ -58,6 +58,14 @@ typedef enum {
 
 typedef enum { SDD_FP64 = 0, SDD_FP32 = 1 } sdd_precision;
 
+/* Exit test of a walk step (Sec. 2.2).  END_OF_STEP: the path exits when a
+ * step ends on or outside the square.  BRIDGE: in addition, a step whose
+ * ends are both inside exits with the probability that the Brownian bridge
+ * between them left the square (Sec. 2.2 notes that this conditional
+ * probability greatly reduces the error of plain stepping near the
+ * boundary). */
+typedef enum { SDD_EXIT_END_OF_STEP = 0, SDD_EXIT_BRIDGE = 1 } sdd_exit_test;
+
 /* Density terms; w = base + sum_t amp_t f_t with amp_t >= 0 and base > 0,
  * so w >= base > 0 as eq. (5) requires.  With d = (xi - cx, eta - cy) and
  * s = coef * (nx d_xi + ny d_eta):
@@ -154,7 +162,20 @@ void sdd_destroy(sdd_ctx* ctx);
  * double in both modes, and its value is the boundary map there.  A path
  * still inside after ceil(t_max/dt) steps, rounded up to an even count, is
  * capped: it takes the value at the nearest boundary point and is counted
- * in stats->capped.  Per-node sums are accumulated in double with
+ * in stats->capped.
+ *
+ * exit_test SDD_EXIT_BRIDGE adds, after a step P -> Q with both ends inside,
+ * the bridge test: each coordinate of the Brownian bridge from P to Q is an
+ * independent one-dimensional bridge with diffusion coefficient 2, which
+ * hits a wall it starts a and ends b away from with probability
+ * exp(-a b / dt).  Per axis the nearer wall counts, and the step exits with
+ * probability p_xi + p_eta - p_xi p_eta (computed as one fma), compared with
+ * the uniform u = (b + 1/2) 2^-18, b = (r_a >> 23) | (r_b >> 23) << 9, from
+ * the nine high bits of the step's two words (the normals use the low 23).
+ * A bridged exit leaves through the nearer wall of the axis with the larger
+ * probability (xi on ties), at Q moved onto that wall; these decisions are
+ * taken in the walk precision.  Its bias in the exit point is O(dt) where
+ * the end-of-step test's is O(sqrt dt).  Per-node sums are accumulated in double with
  * compensation, in a fixed order, so results do not depend on scheduling.
  * The workspace holds every path's last step (16 bytes in float, 32 in
  * double) and step count (4 bytes): n_nodes * N must stay below
@@ -163,8 +184,9 @@ void sdd_destroy(sdd_ctx* ctx);
  *   w, bmap      host structs (bmap->table, if any, is device memory)
  *   nodes        device [n_nodes][2], every point strictly inside (0,1)^2
  *   paths_per_node  N >= 1; paths path_begin .. path_begin+N-1 are walked
- *   dt           0 < dt < 1, and ceil(t_max/dt) < 2^31
+ *   dt           0 < dt < 1, and ceil(t_max/dt) < 2^28 - 2
  *   t_max        step cap in time units; <= 0 selects 8
+ *   exit_test    sdd_exit_test
  *   mean         device [n][2]   sum / N
  *   se           device [n][2] or NULL: sqrt(max(0, S2 - N mean^2) / (N(N-1))),
  *                0 when N = 1
@@ -180,8 +202,9 @@ size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec
 sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap,
                                   const double* nodes, int64_t n_nodes, int64_t paths_per_node,
                                   int64_t path_begin, double dt, uint64_t seed, int32_t prec, double t_max,
-                                  double* mean, double* se, double* sums, sdd_walk_stats* stats,
-                                  sdd_path_record* per_path, void* workspace, size_t ws_bytes, void* stream);
+                                  int32_t exit_test, double* mean, double* se, double* sums,
+                                  sdd_walk_stats* stats, sdd_path_record* per_path, void* workspace,
+                                  size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------- interfaces ---
  * Interface points of a layout (Sec. 2.1, Fig. 1): the (sx-1)(sy-1)

@@ -22,6 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libsdd.so")
 
 SDD_FP64, SDD_FP32 = 0, 1
 PREC = {"fp64": SDD_FP64, "fp32": SDD_FP32}
+SDD_EXIT_END_OF_STEP, SDD_EXIT_BRIDGE = 0, 1
+EXIT_TEST = {"step": SDD_EXIT_END_OF_STEP, "bridge": SDD_EXIT_BRIDGE}
 TERM = {"gauss": 0, "ring": 1, "sech2": 2, "sin2": 3}
 BMAP = {"identity": 0, "affine": 1, "annulus": 2, "table": 3}
 PLACEMENT = {"uniform": 0, "equidistributed": 1}
@@ -96,7 +98,7 @@ def lib() -> C.CDLL:
     L.sdd_workspace_bytes.argtypes = [I64, I64, I32]
     L.sdd_workspace_bytes.restype = SZ
     L.sdd_interface_estimate.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), P, I64, I64, I64, D, U64,
-                                         I32, D, P, P, P, P, P, P, SZ, P]
+                                         I32, D, I32, P, P, P, P, P, P, SZ, P]
     L.sdd_interface_estimate.restype = C.c_int
     L.sdd_layout_node_count.argtypes = [C.POINTER(sdd_layout), I32]
     L.sdd_layout_node_count.restype = I64
@@ -256,9 +258,11 @@ def sdd_workspace_bytes(n_nodes: int, paths_per_node: int, prec: str = "fp64") -
 def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_node: int, dt: float, seed: int,
                            prec: str = "fp64", t_max: float = 8.0, path_begin: int = 0, want_se: bool = True,
                            want_sums: bool = False, want_stats: bool = True, per_path: bool = False,
-                           stream=None, out: Optional[dict] = None) -> dict:
+                           stream=None, out: Optional[dict] = None, exit_test: str = "step") -> dict:
     """Monte Carlo estimate at every node (device tensors in, device tensors out).
 
+    exit_test: "step" (end-of-step test) or "bridge" (plus the Brownian-bridge
+    test).
     nodes: device float64 [n, 2].  Returns dict with 'mean' [n,2], and as
     requested 'se' [n,2], 'sums' [n,4], 'stats' (int64 [3]: steps, paths,
     capped) and 'per_path' (uint8 [n, N, 32] records).  Results are valid
@@ -286,8 +290,9 @@ def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_n
     ws = ctx.workspace(wsb)
     rc = lib().sdd_interface_estimate(
         ctx.h, C.byref(D), C.byref(B.s), _ptr(nodes), n, int(paths_per_node), int(path_begin), float(dt),
-        C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), PREC[prec], float(t_max), _ptr(o["mean"]), _ptr(o.get("se")),
-        _ptr(o.get("sums")), _ptr(o.get("stats")), _ptr(o.get("per_path")), _ptr(ws), ws.numel(), _stream(stream))
+        C.c_uint64(int(seed) & 0xFFFFFFFFFFFFFFFF), PREC[prec], float(t_max), EXIT_TEST[exit_test],
+        _ptr(o["mean"]), _ptr(o.get("se")), _ptr(o.get("sums")), _ptr(o.get("stats")), _ptr(o.get("per_path")),
+        _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "sdd_interface_estimate")
     o["_bmap"] = B
     return o
@@ -381,7 +386,7 @@ def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -
     L = cfg["layout"]
     nodes = sdd_layout_nodes(ctx, L, cfg["k"], cfg.get("placement", "uniform"), dens, stream=stream)
     est = sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
-                                 per_path=per_path, stream=stream)
+                                 per_path=per_path, stream=stream, exit_test=cfg.get("exit_test", "step"))
     vert, horiz = sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"),
                                       stream=stream)
     sol = sdd_subdomain_solve(ctx, dens, B, L, vert, horiz, stream=stream)

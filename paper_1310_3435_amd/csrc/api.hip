@@ -76,7 +76,8 @@ size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec
 
 sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const double* nodes,
                                   int64_t n_nodes, int64_t paths_per_node, int64_t path_begin, double dt,
-                                  uint64_t seed, int32_t prec, double t_max, double* mean, double* se, double* sums,
+                                  uint64_t seed, int32_t prec, double t_max, int32_t exit_test, double* mean,
+                                  double* se, double* sums,
                                   sdd_walk_stats* stats, sdd_path_record* per_path, void* workspace, size_t ws_bytes,
                                   void* stream)
 {
@@ -89,10 +90,11 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
     if (path_begin + paths_per_node > ((int64_t)1 << 32)) return SDD_EINVAL;
     if (!(dt > 0.0) || !(dt < 1.0)) return SDD_EINVAL;
     if (prec != SDD_FP32 && prec != SDD_FP64) return SDD_EINVAL;
+    if (exit_test != SDD_EXIT_END_OF_STEP && exit_test != SDD_EXIT_BRIDGE) return SDD_EINVAL;
     if (!(t_max > 0.0)) t_max = 8.0;
     if (!is_finite(t_max)) return SDD_EINVAL;
     double kd = ceil(t_max / dt);
-    if (!(kd >= 1.0) || kd >= 2147483640.0) return SDD_EINVAL;
+    if (!(kd >= 1.0) || kd >= (double)(kMaxSteps - 1)) return SDD_EINVAL;
     kd += fmod(kd, 2.0);  // the cap is rounded up to an even step count
     const WalkWorkspace W = walk_workspace(n_nodes, paths_per_node, prec);
     if (ws_bytes < W.bytes) return SDD_ENOSPC;
@@ -111,6 +113,7 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
     A.dt = dt;
     A.sqrt2dt = sqrt(2.0 * dt);
     A.noise_f32 = sqrt(2.0 * dt) * sqrt(2.0 * 0.69314718055994530942);
+    A.bridge = exit_test == SDD_EXIT_BRIDGE ? 1 : 0;
     A.key0 = (uint32_t)seed;
     A.key1 = (uint32_t)(seed >> 32);
     char* ws = (char*)workspace;

@@ -24,12 +24,20 @@ struct WalkArgs {
     double dt;
     double sqrt2dt;
     double noise_f32;    // sqrt(2 dt) sqrt(2 ln 2): the float walk's normals come scaled
+    int32_t bridge;      // 1: Brownian-bridge exit test after every step
     uint32_t key0, key1;
     void* pq;                     // [total] (P.x, P.y, Q.x, Q.y) of the last step, walk precision
-    uint32_t* info;               // [total] exit step | capped << 31
+    uint32_t* info;               // [total] exit step | side << 28 | bridged << 30 | capped << 31
     unsigned long long* counter;  // ticket counter, zeroed before the walk
     sdd_path_record* per_path;    // optional [total]
 };
+
+// Per-path info word written by the walk.
+constexpr uint32_t kInfoSteps = 0x0fffffffu;
+constexpr uint32_t kInfoBridged = 0x40000000u;
+constexpr uint32_t kInfoCapped = 0x80000000u;
+constexpr int kInfoSideShift = 28;
+constexpr int64_t kMaxSteps = (int64_t)kInfoSteps;
 
 // Workspace carving of sdd_interface_estimate.
 struct WalkWorkspace {

@@ -87,5 +87,50 @@ __device__ __forceinline__ bool outside(float x, float y)
 }
 __device__ __forceinline__ bool outside(double x, double y) { return x <= 0.0 || x >= 1.0 || y <= 0.0 || y >= 1.0; }
 
+// Brownian-bridge exit test of one step P -> Q with both ends inside (the
+// conditional exit probability of Sec. 2.2).  Each coordinate of the bridge
+// is an independent one-dimensional bridge with diffusion coefficient 2, and
+// one that starts a and ends b away from a wall hits it within dt with
+// probability exp(-a b / dt); per axis the nearer wall counts, and the step
+// exits with probability p_xi + p_eta - p_xi p_eta.  The uniform compared
+// with it comes from the nine high bits of each of the step's two words,
+// which the normals do not use: u = (b + 1/2) 2^-18 with
+// b = (ra >> 23) | (rb >> 23) << 9.
+//
+// Float: c = -log2(e) / dt, and u is built as the bit pattern 1 + b 2^-18
+// minus (1 - 2^-19), an exact subtraction.
+__device__ __forceinline__ bool bridge_exit(float px, float py, float qx, float qy, uint32_t ra, uint32_t rb,
+                                            float c)
+{
+    const float mx = __builtin_fminf(px * qx, (1.0f - px) * (1.0f - qx));
+    const float my = __builtin_fminf(py * qy, (1.0f - py) * (1.0f - qy));
+    const float pxi = __builtin_amdgcn_exp2f(mx * c), peta = __builtin_amdgcn_exp2f(my * c);
+    const float p = __builtin_fmaf(-pxi, peta, pxi + peta);
+    const uint32_t bits = ((ra >> 18) & 0x00003fe0u) | ((rb >> 9) & 0x007fc000u) | 0x3f800000u;
+    return __uint_as_float(bits) - 0x1.fffffcp-1f < p;
+}
+
+// Double: c = dt.
+__device__ __forceinline__ bool bridge_exit(double px, double py, double qx, double qy, uint32_t ra, uint32_t rb,
+                                            double c)
+{
+    const double m0 = px * qx, m1 = (1.0 - px) * (1.0 - qx);
+    const double m2 = py * qy, m3 = (1.0 - py) * (1.0 - qy);
+    const double pxi = exp(-(m0 <= m1 ? m0 : m1) / c), peta = exp(-(m2 <= m3 ? m2 : m3) / c);
+    const double p = __builtin_fma(-pxi, peta, pxi + peta);
+    const uint32_t b = (ra >> 23) | ((rb >> 23) << 9);
+    return ((double)b + 0.5) * 0x1p-18 < p;
+}
+
+// Side a bridged exit leaves through: the nearer wall of the axis with the
+// larger probability, xi on ties (the walk's own precision decides).
+template <typename R>
+__device__ __forceinline__ uint32_t bridge_side(R px, R py, R qx, R qy)
+{
+    const R m0 = px * qx, m1 = (R(1) - px) * (R(1) - qx);
+    const R m2 = py * qy, m3 = (R(1) - py) * (R(1) - qy);
+    const R mx = m0 <= m1 ? m0 : m1, my = m2 <= m3 ? m2 : m3;
+    return mx <= my ? (m0 <= m1 ? 0u : 1u) : (m2 <= m3 ? 2u : 3u);
+}
 
 }  // namespace sdd

@@ -6,8 +6,10 @@
 // belongs to, so lanes stay busy until the ticket range is exhausted.  A
 // loop iteration is one Philox block, i.e. two Euler-Maruyama steps (Sec.
 // 2.2) with an exit test after each; a path always starts at an even step.
+// With the Brownian-bridge option the step also exits, with the bridge's
+// conditional probability, when both its ends are inside (rng.h).
 // At exit the lane stores the last step's endpoints P, Q and the step count
-// in the path's own slot.  A second kernel projects P -> Q onto the boundary
+// (with the side of a bridged exit) in the path's own slot.  A second kernel projects P -> Q onto the boundary
 // in double, evaluates the boundary map there (eq. (7a)) and reduces each
 // node's paths in a fixed order, so every result is independent of the
 // schedule, and the walk keeps no double-precision state.
@@ -68,13 +70,18 @@ __device__ __forceinline__ void load_pq(const void* pq, size_t t, double, double
 constexpr uint32_t kTicketBatch = 64;
 constexpr int kWalkBlock = 256;
 
-template <typename R, int KIND>
+// Constant of the bridge test: -log2(e)/dt in float, dt in double.
+__device__ __forceinline__ float bridge_const(const WalkArgs& A, float) { return (float)(-1.4426950408889634 / A.dt); }
+__device__ __forceinline__ double bridge_const(const WalkArgs& A, double) { return A.dt; }
+
+template <typename R, int KIND, bool BRIDGE>
 __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
 {
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t N = (uint32_t)A.paths;
     const R dt = (R)A.dt;
     const R sd = noise_scale(A, R(0));
+    const R bc = bridge_const(A, R(0));
 
     // wave-uniform ticket pool
     uint32_t pool_lo = 0, pool_hi = 0;
@@ -143,15 +150,24 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
         // the step cap is even, so it can only fall after step 2m+1
         const bool outA = outside(XA, YA);
         const bool outB = outside(XB, YB);
-        const bool fin = live && (outA || outB || (k + 2 >= A.kmax));
+        bool exA = outA, exB = outB;
+        if constexpr (BRIDGE) {
+            exA = outA || bridge_exit(X, Y, XA, YA, r.x, r.y, bc);
+            exB = outB || bridge_exit(XA, YA, XB, YB, r.z, r.w, bc);
+        }
+        const bool fin = live && (exA || exB || (k + 2 >= A.kmax));
 
         if (fin) {
             // the exit projection and boundary map run in the reduction
-            if (outA)
-                store_pq(A, t, X, Y, XA, YA);
-            else
-                store_pq(A, t, XA, YA, XB, YB);
-            A.info[t] = (uint32_t)(outA ? k + 1 : k + 2) | ((outA || outB) ? 0u : 0x80000000u);
+            const R px = exA ? X : XA, py = exA ? Y : YA;
+            const R qx = exA ? XA : XB, qy = exA ? YA : YB;
+            store_pq(A, t, px, py, qx, qy);
+            uint32_t w = (uint32_t)(exA ? k + 1 : k + 2);
+            if (!(exA || exB))
+                w |= kInfoCapped;
+            else if (BRIDGE && !(exA ? outA : outB))
+                w |= kInfoBridged | (bridge_side(px, py, qx, qy) << kInfoSideShift);
+            A.info[t] = w;
             live = false;
         }
         // finished and idle lanes carry garbage until their next start
@@ -191,8 +207,16 @@ __global__ __launch_bounds__(kReduceBlock) void reduce_kernel(const void* __rest
         double px, py, qx, qy, ex, ey;
         load_pq(pq, t, R(0), px, py, qx, qy);
         const uint32_t w = in_info(info, t);
-        const bool capped = (w >> 31) != 0;
-        const int side = capped ? nearest_side(qx, qy, ex, ey) : exit_point(px, py, qx, qy, ex, ey);
+        const bool capped = (w & kInfoCapped) != 0;
+        int side;
+        if (w & kInfoBridged) {
+            // bridged exit: the end of the step moved onto the wall it crossed
+            side = (int)((w >> kInfoSideShift) & 3u);
+            ex = side == 0 ? 0.0 : side == 1 ? 1.0 : qx;
+            ey = side == 2 ? 0.0 : side == 3 ? 1.0 : qy;
+        } else {
+            side = capped ? nearest_side(qx, qy, ex, ey) : exit_point(px, py, qx, qy, ex, ey);
+        }
         double x, y;
         bmap_eval(B, side, ex, ey, x, y);
         if (px != px) x = y = px;  // node off the square: NaN
@@ -200,13 +224,13 @@ __global__ __launch_bounds__(kReduceBlock) void reduce_kernel(const void* __rest
         nadd(s[1], c[1], y);
         nadd(s[2], c[2], x * x);
         nadd(s[3], c[3], y * y);
-        st += w & 0x7fffffffu;
-        cp += w >> 31;
+        st += w & kInfoSteps;
+        cp += capped ? 1 : 0;
         if (per_path) {
             sdd_path_record* rec = per_path + t;
             rec->exit_xi = ex;
             rec->exit_eta = ey;
-            rec->steps = w & 0x7fffffffu;
+            rec->steps = w & kInfoSteps;
             rec->side = side;
             rec->capped = capped ? 1 : 0;
         }
@@ -292,7 +316,7 @@ __global__ __launch_bounds__(1024) void stats_kernel(const long long* __restrict
     }
 }
 
-template <typename R, int KIND>
+template <typename R, int KIND, bool BRIDGE>
 static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
 {
     // a persistent grid of 4 waves per SIMD (SDD_WALK_WAVES_PER_SIMD
@@ -308,7 +332,7 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, walk_kernel<R, KIND>, kWalkBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, walk_kernel<R, KIND, BRIDGE>, kWalkBlock, 0) != hipSuccess ||
             occ <= 0)
             occ = 2;
         int want = 4;  // blocks of 4 waves: one wave per SIMD each
@@ -322,21 +346,27 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     const int64_t most = (need + kWalkBlock / kWave - 1) / (kWalkBlock / kWave);
     if (blocks > most) blocks = most;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((walk_kernel<R, KIND>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, stream, A);
+    hipLaunchKernelGGL((walk_kernel<R, KIND, BRIDGE>), dim3((unsigned)blocks), dim3(kWalkBlock), 0, stream, A);
     return hipGetLastError();
+}
+
+template <typename R, bool BRIDGE>
+static hipError_t launch_walk_kind(const WalkArgs& A, hipStream_t stream)
+{
+    const int kind = A.dens.n_terms == 1 ? A.dens.kind[0] : kAnyTerms;
+    switch (kind) {
+    case SDD_TERM_GAUSS: return launch_walk_kernel<R, SDD_TERM_GAUSS, BRIDGE>(A, stream);
+    case SDD_TERM_RING: return launch_walk_kernel<R, SDD_TERM_RING, BRIDGE>(A, stream);
+    case SDD_TERM_SECH2: return launch_walk_kernel<R, SDD_TERM_SECH2, BRIDGE>(A, stream);
+    case SDD_TERM_SIN2: return launch_walk_kernel<R, SDD_TERM_SIN2, BRIDGE>(A, stream);
+    default: return launch_walk_kernel<R, kAnyTerms, BRIDGE>(A, stream);
+    }
 }
 
 template <typename R>
 static hipError_t launch_walk_prec(const WalkArgs& A, hipStream_t stream)
 {
-    const int kind = A.dens.n_terms == 1 ? A.dens.kind[0] : kAnyTerms;
-    switch (kind) {
-    case SDD_TERM_GAUSS: return launch_walk_kernel<R, SDD_TERM_GAUSS>(A, stream);
-    case SDD_TERM_RING: return launch_walk_kernel<R, SDD_TERM_RING>(A, stream);
-    case SDD_TERM_SECH2: return launch_walk_kernel<R, SDD_TERM_SECH2>(A, stream);
-    case SDD_TERM_SIN2: return launch_walk_kernel<R, SDD_TERM_SIN2>(A, stream);
-    default: return launch_walk_kernel<R, kAnyTerms>(A, stream);
-    }
+    return A.bridge ? launch_walk_kind<R, true>(A, stream) : launch_walk_kind<R, false>(A, stream);
 }
 
 hipError_t launch_walk(const WalkArgs& A, int prec, double* mean, double* se, double* sums, sdd_walk_stats* stats,
