@@ -100,17 +100,20 @@ def cpu_baseline(cfg, nodes, sample_nodes: int):
             "nodes_per_s": sample_nodes / el}
 
 
-def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4):
-    """Config-4 style serving: a burst of `burst` requests measures capacity
+def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, bridge_dt: float = 0.0):
+    """Serving stream: a burst of `burst` requests measures capacity
     (requests/s at saturation); then `n_requests` arrive as a Poisson stream
     at `load` x capacity.  Latency = arrival (submit) to the mesh being in
-    host memory, on the server's clock."""
+    host memory, on the server's clock.  bridge_dt > 0: every request uses
+    the Brownian-bridge exit test at that time step instead."""
     import numpy as np
 
     import paper_1310_3435_amd as sdd
     import workloads
 
     reqs = workloads.serving_requests(n_requests + burst, master_seed=seed)
+    if bridge_dt > 0:
+        reqs = [dict(r, exit_test="bridge", dt=bridge_dt) for r in reqs]
     srv = sdd.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=64, max_nodes=4096, max_points=257 * 257)
     try:
         t0 = srv.clock()
@@ -150,7 +153,8 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4):
         "walk_steps_per_s": steps / wall, "median_paths_per_node": float(np.median([r["paths_per_node"] for r in ok])),
         "max_se": float(max(r["max_se"] for r in ok)),
         "stream": "1-4 Gaussian bumps (amp U[1,20], width U[20,200]), grids {33,65,129,257}^2, 2x2..8x8 "
-                  "subdomains, SE 1e-3 per node, dt 1e-4, float walks, Poisson arrivals",
+                  "subdomains, SE 1e-3 per node, float walks, Poisson arrivals, "
+                  + (f"bridge exit test at dt {bridge_dt:g}" if bridge_dt > 0 else "end-of-step exit test at dt 1e-4"),
     }
 
 
@@ -269,6 +273,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / measured capacity")
     ap.add_argument("--serve-burst", type=int, default=16, help="requests of the capacity burst")
+    ap.add_argument("--serve-bridge-dt", type=float, default=0.0,
+                    help="> 0: serving requests use the bridge exit test at this time step")
     ap.add_argument("--bias-sweep", action="store_true",
                     help="only run the float/double dt sweep of the closed-form workload")
     ap.add_argument("--sweep-paths", type=int, default=1000000)
@@ -419,7 +425,8 @@ def main():
         line["bridge"] = bridge_legs(ctx, cfg, B, nodes, float(np.mean(walk_ms)), steps_per_pass,
                                      est["mean"].cpu().numpy(), args.bridge_paths)
     if args.serve_requests > 0:
-        line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst)
+        line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst,
+                                     bridge_dt=args.serve_bridge_dt)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes)
     print(json.dumps(line), flush=True)

@@ -285,7 +285,8 @@ sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bma
  * bitwise the same alone or in any mix.
  *
  * Requests walk in float (compensated double sums, double exit
- * projection); the density must be a sum of up to four GAUSS terms; the
+ * projection) with the exit test of sdd_interface_estimate that
+ * exit_test names; the density must be a sum of up to four GAUSS terms; the
  * boundary map IDENTITY, AFFINE or ANNULUS.  A request's device footprint
  * (nodes, sums, interface lines, mesh, subdomain workspace) comes from an
  * arena of hbm_budget_bytes allocated once at creation; a request is
@@ -301,7 +302,7 @@ typedef struct {
     int32_t k;          /* interface points per segment */
     int32_t placement;  /* 0 uniform, 1 equidistributed */
     int32_t interp;     /* 0 linear, 1 monotone cubic */
-    int32_t pad;
+    int32_t exit_test;  /* sdd_exit_test */
     double dt;
     double se_target;       /* > 0: paths from a pilot; <= 0: paths_per_node */
     int64_t paths_per_node; /* used when se_target <= 0 */

@@ -60,7 +60,7 @@ class sdd_walk_stats(C.Structure):
 
 class sdd_request(C.Structure):
     _fields_ = [("w", sdd_density), ("bmap", sdd_bmap), ("layout", sdd_layout), ("k", C.c_int32),
-                ("placement", C.c_int32), ("interp", C.c_int32), ("pad", C.c_int32), ("dt", C.c_double),
+                ("placement", C.c_int32), ("interp", C.c_int32), ("exit_test", C.c_int32), ("dt", C.c_double),
                 ("se_target", C.c_double), ("paths_per_node", C.c_int64), ("seed", C.c_uint64),
                 ("t_max", C.c_double)]
 
@@ -408,6 +408,7 @@ def make_request(req: dict) -> sdd_request:
     R.k = int(req["k"])
     R.placement = PLACEMENT[req.get("placement", "uniform")]
     R.interp = INTERP[req.get("interp", "linear")]
+    R.exit_test = EXIT_TEST[req.get("exit_test", "step")]
     R.dt = float(req["dt"])
     R.se_target = float(req.get("se_target", 0.0))
     R.paths_per_node = int(req.get("paths", 0))

@@ -45,6 +45,8 @@ struct ServeReq {
     int32_t n_terms;
     float cx[kServeTerms], cy[kServeTerms], k2[kServeTerms], la[kServeTerms], m2c[kServeTerms];
     float dt, noise;
+    float bridge_c;   // -log2(e)/dt
+    int32_t bridge;   // 1: Brownian-bridge exit test
     int32_t kmax;
     uint32_t key0, key1;
     uint32_t n_nodes;
@@ -96,8 +98,9 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
     float X = 0, Y = 0;
     int32_t k = 0;
     // the lane's request
-    float fbase = 1, dt = 0, sd = 0;
+    float fbase = 1, dt = 0, sd = 0, bc = 0;
     int32_t nterm = 0, kmax = 0;
+    bool bridge = false;
     uint32_t key0 = 0, key1 = 0;
     float cx[kServeTerms], cy[kServeTerms], k2[kServeTerms], la[kServeTerms], m2c[kServeTerms];
 #pragma unroll
@@ -145,6 +148,8 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
                 }
                 dt = R->dt;
                 sd = R->noise;
+                bc = R->bridge_c;
+                bridge = R->bridge != 0;
                 kmax = R->kmax;
                 key0 = R->key0;
                 key1 = R->key1;
@@ -203,10 +208,22 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
         }
         const bool outA = outside(XA, YA);
         const bool outB = outside(XB, YB);
-        const bool fin = live && (outA || outB || (k + 2 >= kmax));
+        bool exA = outA, exB = outB;
+        if (__ballot(live && bridge) != 0) {
+            // some lane's request asks for the bridge test (wave-uniform branch)
+            exA = outA || (bridge && bridge_exit(X, Y, XA, YA, r.x, r.y, bc));
+            exB = outB || (bridge && bridge_exit(XA, YA, XB, YB, r.z, r.w, bc));
+        }
+        const bool fin = live && (exA || exB || (k + 2 >= kmax));
         if (fin) {
-            pq[rec] = outA ? make_float4(X, Y, XA, YA) : make_float4(XA, YA, XB, YB);
-            info[rec] = (uint32_t)(outA ? k + 1 : k + 2) | ((outA || outB) ? 0u : 0x80000000u);
+            const float px = exA ? X : XA, py = exA ? Y : YA, qx = exA ? XA : XB, qy = exA ? YA : YB;
+            pq[rec] = make_float4(px, py, qx, qy);
+            uint32_t w = (uint32_t)(exA ? k + 1 : k + 2);
+            if (!(exA || exB))
+                w |= kInfoCapped;
+            else if (!(exA ? outA : outB))
+                w |= kInfoBridged | (bridge_side(px, py, qx, qy) << kInfoSideShift);
+            info[rec] = w;
             live = false;
         }
         X = XB;
@@ -245,16 +262,23 @@ __global__ __launch_bounds__(kServeBlock) void serve_reduce_kernel(const ServeSe
             const float4 v = pq[base + j];
             const uint32_t w = info[base + j];
             double ex, ey;
-            const bool capped = (w >> 31) != 0;
-            const int side = capped ? nearest_side(v.z, v.w, ex, ey) : exit_point(v.x, v.y, v.z, v.w, ex, ey);
+            const bool capped = (w & kInfoCapped) != 0;
+            int side;
+            if (w & kInfoBridged) {
+                side = (int)((w >> kInfoSideShift) & 3u);
+                ex = side == 0 ? 0.0 : side == 1 ? 1.0 : (double)v.z;
+                ey = side == 2 ? 0.0 : side == 3 ? 1.0 : (double)v.w;
+            } else {
+                side = capped ? nearest_side(v.z, v.w, ex, ey) : exit_point(v.x, v.y, v.z, v.w, ex, ey);
+            }
             double x, y;
             bmap_eval(B, side, ex, ey, x, y);
             nadd(sm[0], cm[0], x);
             nadd(sm[1], cm[1], y);
             nadd(sm[2], cm[2], x * x);
             nadd(sm[3], cm[3], y * y);
-            st += w & 0x7fffffffu;
-            cp += w >> 31;
+            st += w & kInfoSteps;
+            cp += capped ? 1 : 0;
         }
         double tot[4];
 #pragma unroll
@@ -472,7 +496,8 @@ sdd_status check_request(const sdd_server* S, const sdd_request* q, int64_t& n_n
     if (!(q->dt > 0.0) || !(q->dt < 1.0)) return SDD_EINVAL;
     if (!(q->se_target > 0.0) && q->paths_per_node < 2) return SDD_EINVAL;
     const double tmax = q->t_max > 0.0 ? q->t_max : 8.0;
-    if (!is_finite(tmax) || ceil(tmax / q->dt) >= 2147483640.0) return SDD_EINVAL;
+    if (!is_finite(tmax) || ceil(tmax / q->dt) >= (double)(kMaxSteps - 1)) return SDD_EINVAL;
+    if (q->exit_test != SDD_EXIT_END_OF_STEP && q->exit_test != SDD_EXIT_BRIDGE) return SDD_EINVAL;
     const sdd_layout& L = q->layout;
     n_nodes = (int64_t)(L.sx - 1) * (L.sy - 1) + (int64_t)q->k * ((int64_t)(L.sx - 1) * L.sy + (int64_t)(L.sy - 1) * L.sx);
     if (n_nodes < 1 || n_nodes > S->max_nodes) return SDD_EINVAL;
@@ -497,6 +522,8 @@ void fill_serve_req(const sdd_request& q, const double* nodes, uint32_t n_nodes,
     }
     R.dt = (float)q.dt;
     R.noise = (float)(sqrt(2.0 * q.dt) * sqrt(2.0 * 0.69314718055994530942));
+    R.bridge_c = (float)(-1.4426950408889634 / q.dt);
+    R.bridge = q.exit_test == SDD_EXIT_BRIDGE ? 1 : 0;
     const double tmax = q.t_max > 0.0 ? q.t_max : 8.0;
     double kd = ceil(tmax / q.dt);
     kd += fmod(kd, 2.0);

@@ -135,3 +135,34 @@ def test_rejected_requests(ctx):
         assert ok["status"] == 0
     finally:
         srv.close()
+
+
+def test_bridge_request_alone_in_a_mix_and_against_the_oracle(ctx, ref):
+    import paper_1310_3435_amd as sdd
+    req = dict(small_request(seed=21, paths=2048, se=0.0), dt=1e-3, exit_test="bridge")
+    srv = sdd.Server(ctx, hbm_budget_bytes=256 << 20, max_slots=16)
+    try:
+        say("serve: bridge request alone")
+        alone = srv.wait(srv.submit(req))
+        mix = W.serving_requests(12, master_seed=13, grids=(33, 65), splits=(2, 4))
+        ids = [srv.submit(dict(r, exit_test="bridge" if i % 2 else "step")) for i, r in enumerate(mix[:6])]
+        tid = srv.submit(req)
+        ids += [srv.submit(r) for r in mix[6:]]
+        say("serve: bridge request in a mix of step and bridge requests")
+        res = [srv.wait(i) for i in ids]
+        mixed = srv.wait(tid)
+    finally:
+        srv.close()
+    assert alone["status"] == 0 and mixed["status"] == 0 and all(r["status"] == 0 for r in res)
+    assert np.array_equal(mixed["mesh"], alone["mesh"]) and mixed["steps"] == alone["steps"]
+    cfg = dict(req, paths=2048, prec="fp64")
+    r64 = ref.pipeline(cfg)
+    se = r64["est"]["se"].max()
+    diff = np.abs(alone["mesh"] - r64["mesh"]).max()
+    r32 = ref.pipeline(dict(cfg, prec="fp32"))
+    d32 = np.abs(alone["mesh"] - r32["mesh"]).max()
+    plain = ref.pipeline(dict(cfg, exit_test="step"))
+    shift = np.abs(plain["mesh"] - r64["mesh"]).max()
+    say(f"served bridge vs oracle: double {diff:.3e}, float {d32:.3e} (SE {se:.3e}); bridge moved the mesh {shift:.3e}")
+    assert diff <= 3 * se and d32 <= 0.5 * se
+    assert shift > 3 * se          # at this dt the bridge changes the mesh well beyond the noise

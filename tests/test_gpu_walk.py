@@ -90,7 +90,7 @@ def test_fp32_walk_matches_oracle_float_walk_and_double_estimates(ctx, ref):
     assert flips.mean() < 2e-3
     assert q[1] < 1e-5 and dmax < 1e-2
     assert g["capped"] == 0 and np.all(np.isfinite(gp["exit_xi"]))
-    # spec criterion: within 3 standard errors of the double oracle
+    # the stated accuracy bar: within 3 standard errors of the double oracle
     z64 = np.abs(g["mean"] - r64["mean"]) / r64["se"]
     say(f"fp32 vs fp64 oracle: max |diff|/SE = {z64.max():.3f}, max |diff| = {np.abs(g['mean'] - r64['mean']).max():.3e}")
     assert np.all(z64 <= 3.0)
