@@ -18,7 +18,7 @@
  *   O(N^-1/2)).
  *   Decomposition (Sec. 2.1, Fig. 1): the estimate is evaluated only at
  *   interface points; the interfaces are completed by interpolation
- *   (Sec. 3.5) and every subdomain is then solved once, independently, by
+ *   (Sec. 3.6) and every subdomain is then solved once, independently, by
  *   centred finite differences (Sec. 3.2).
  *
  * Conventions for every entry point:
@@ -215,7 +215,7 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
  * placement 0 (uniform): s_i = a + (b-a) i/(k+1) on segment [a, b];
  * placement 1 (equidistributed): int_a^{s_i} w ds = i/(k+1) int_a^b w ds,
  * with the integral by Simpson's rule on 4096 panels and linear inversion
- * inside a panel (the paper places points from the density, Sec. 3.5).
+ * inside a panel (the paper places points from the density, Sec. 3.6).
  * nodes: device [sdd_layout_node_count(L, k)][2].  w may be NULL for
  * placement 0. */
 int64_t sdd_layout_node_count(const sdd_layout* L, int32_t k);
@@ -232,7 +232,7 @@ sdd_status sdd_layout_nodes(sdd_ctx* ctx, const sdd_layout* L, int32_t k, int32_
 sdd_status sdd_bmap_edge1d_table(sdd_ctx* ctx, const sdd_density* w, int32_t n_per_edge, double* table,
                                  void* stream);
 
-/* Interface completion (Sec. 3.5: Monte Carlo at a few points plus
+/* Interface completion (Sec. 3.6: Monte Carlo at a few points plus
  * interpolation).  values: device [node_count][2], the estimates at `nodes`
  * (layout order above).  Every segment is interpolated through (start, its
  * k points, end) in the segment parameter: interp 0 linear, interp 1

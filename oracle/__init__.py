@@ -15,13 +15,15 @@ Parts (Bihlo & Haynes, arXiv 1310.3435):
   reference).
 * ``layout_nodes`` -- interface points of a non-overlapping decomposition
   (Sec. 2.1, Fig. 1), uniformly spaced or equidistributing w along each
-  segment (Sec. 3.5 places the points from the monitor function).
+  segment (Sec. 3.6 places the points from the monitor function).
 * ``fill_interfaces`` -- Monte Carlo values at a few points plus
-  interpolation along each interface (Sec. 3.5), linear or monotone cubic.
+  interpolation along each interface (Sec. 3.6), linear or monotone cubic.
 * ``subdomain_solve`` -- the independent Dirichlet solves of every
   subdomain by centred finite differences (Sec. 2.1, Sec. 3.2), here solved
   directly by a sparse LU rather than iterated, so that it is the exact
   discrete solution.
+* ``mesh_quality``, ``mesh_compare``, ``perona_malik``,
+  ``smooth_interfaces`` -- quality measure and smoothing (``postprocess.py``).
 
 Every array is float64 and C-contiguous.
 """
@@ -423,7 +425,7 @@ def interp_segment(t: np.ndarray, v: np.ndarray, te: np.ndarray, kind: str) -> n
 
 def fill_interfaces(L: dict, k: int, bmap, nodes: np.ndarray, values: np.ndarray, interp: str,
                     density: Optional[dict] = None) -> Tuple[np.ndarray, np.ndarray]:
-    """All interface mesh values from the node estimates (Sec. 3.5).
+    """All interface mesh values from the node estimates (Sec. 3.6).
 
     Returns (vert[sx-1][ny][2], horiz[sy-1][nx][2]).  Line ends take the
     boundary map, crosspoints their own estimate, segment interiors the
@@ -574,7 +576,8 @@ def global_solve(density: dict, bmap, nx: int, ny: int) -> np.ndarray:
 # ------------------------------------------------------------------ pipeline
 
 def pipeline(cfg: dict, nthreads: int = 0) -> dict:
-    """Nodes -> interface estimate -> fill -> subdomain solves."""
+    """Nodes -> interface estimate -> fill [-> interface smoothing] ->
+    subdomain solves [-> Perona-Malik smoothing]."""
     dens = cfg["density"]
     B = Bmap(cfg["bmap"], dens)
     L = cfg["layout"]
@@ -582,5 +585,14 @@ def pipeline(cfg: dict, nthreads: int = 0) -> dict:
     est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
                              nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge")
     vert, horiz = fill_interfaces(L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"))
+    if cfg.get("smooth_span", 0) > 0:
+        vert, horiz = smooth_interfaces(L, vert, horiz, int(cfg["smooth_span"]))
     mesh = subdomain_solve(dens, B, L, vert, horiz)
+    pm = cfg.get("pm")
+    if pm:
+        mesh = perona_malik(mesh, pm["dt"], pm["k"], pm["steps"], L if pm.get("per_subdomain", True) else None)
     return {"nodes": nodes, "est": est, "vert": vert, "horiz": horiz, "mesh": mesh}
+
+
+from oracle.postprocess import (cell_jacobians, fixed_nodes, ftcs_stable, loess_line, loess_value,  # noqa: E402
+                                mesh_compare, mesh_quality, perona_malik, quality_of, smooth_interfaces)

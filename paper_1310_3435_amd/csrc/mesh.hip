@@ -2,7 +2,7 @@
 // batched finite-difference subdomain solves (gfx950).
 //
 // Sec. 2.1 (Fig. 1): interface points of a non-overlapping decomposition;
-// Sec. 3.5: estimates at a few points plus interpolation along each
+// Sec. 3.6: estimates at a few points plus interpolation along each
 // interface, points placed from the density; Sec. 3.2: centred finite
 // differences for the single-domain and subdomain solves, with tangential
 // boundary values from the one-dimensional generator.

@@ -1,6 +1,6 @@
 """Pins of the oracle's deterministic parts: edge data, node placement,
 interface fill and the finite-difference subdomain solves (Sec. 2.1 Fig. 1,
-Sec. 3.2, Sec. 3.5).
+Sec. 3.2, Sec. 3.6).
 """
 import math
 
