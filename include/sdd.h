@@ -267,6 +267,66 @@ sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bma
                                double* mesh, int32_t* sweeps, double* resid, void* workspace, size_t ws_bytes,
                                void* stream);
 
+/* ------------------------------------------------- quality and smoothing ---
+ * Geometric mesh quality (eq. (11), Sec. 3.1).  For each of the
+ * (nx-1)(ny-1) cells, J is the Jacobian of the cell's bilinear map at its
+ * centre: x_xi = ((x10 + x11) - (x00 + x01)) / (2 h_xi),
+ * x_eta = ((x01 + x11) - (x00 + x10)) / (2 h_eta), y alike, with
+ * h_xi = 1/(nx-1), h_eta = 1/(ny-1) and x_ab the node (i+a, j+b); then
+ * Q = tr(J^T J) / (2 sqrt(det(J^T J))), computed as |J|_F^2 / (2 |det J|).
+ *   mesh  device [ny][nx][2]
+ *   q     device [ny-1][nx-1] or NULL: Q of every cell, row-major
+ *   out   device double[3]: Q_max, Q_mean (Sec. 3.3), the number of cells
+ *         with det J <= 0 (folded or degenerate; a degenerate cell has
+ *         Q = +inf)
+ * Sums run in a fixed order.  workspace: device,
+ * >= sdd_quality_workspace_bytes(nx, ny) (also serves sdd_mesh_compare). */
+size_t sdd_quality_workspace_bytes(int32_t nx, int32_t ny);
+
+sdd_status sdd_mesh_quality(sdd_ctx* ctx, int32_t nx, int32_t ny, const double* mesh, double* q, double* out,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/* Two meshes of the same grid (Sec. 3.3): out[0] = l_inf =
+ * max over nodes |w(mesh_i) - w(ref_i)|, w evaluated at the nodes' physical
+ * positions (meaningful where the physical domain lies in the unit square);
+ * out[1] = the largest Euclidean node displacement.  out: device double[2]. */
+sdd_status sdd_mesh_compare(sdd_ctx* ctx, int32_t nx, int32_t ny, const sdd_density* w, const double* mesh,
+                            const double* ref, double* out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Perona-Malik anisotropic diffusion of the mesh (eq. (12), Sec. 3.4):
+ * each component u in {x, y} of the mesh map over the computational grid
+ * takes `steps` forward-in-time centred-in-space steps of
+ * u_t = div(c grad u), c = exp(-|grad u|^2 / k^2):
+ *   u_P += dt (c_E (u_E - u_P) + c_W (u_W - u_P)) / h_xi^2
+ *        + dt (c_N (u_N - u_P) + c_S (u_S - u_P)) / h_eta^2,
+ * each face coefficient from the one-sided difference across the face,
+ * c_E = exp(-((u_E - u_P) / h_xi)^2 / k^2) (Perona and Malik's
+ * discretisation).  The boundary ring is fixed; with per_subdomain = 1 the
+ * interface lines of L are fixed too, so every subdomain is smoothed on
+ * its own (Sec. 3.5); per_subdomain = 0 smooths the whole grid.
+ * Requires dt (2/h_xi^2 + 2/h_eta^2) <= 1 (then each step is a convex
+ * combination: no new extrema), else SDD_EINVAL.  k > 0, steps >= 0.
+ *   mesh       device [ny][nx][2], smoothed in place
+ *   workspace  device, >= sdd_smooth_workspace_bytes(L) */
+size_t sdd_smooth_workspace_bytes(const sdd_layout* L);
+
+sdd_status sdd_mesh_smooth(sdd_ctx* ctx, const sdd_layout* L, int32_t per_subdomain, double dt, double k,
+                           int32_t steps, double* mesh, void* workspace, size_t ws_bytes, void* stream);
+
+/* Interface pre-smoothing (Sec. 4: interface values smoothed by locally
+ * weighted quadratic least squares before the subdomain solves).  Along
+ * every full interface line (vert, horiz as for sdd_fill_interfaces), each
+ * point except the outer-boundary ends and the crosspoints takes the value
+ * at its own parameter of the quadratic fitted to the `span` points nearest
+ * in index (the window shifted to stay on the line) with tricube weights
+ * (1 - (|t|/d)^3)^3, d the largest |t| in the window (Cleveland's local
+ * regression).  span odd, 5 <= span <= the points of a line.  In place;
+ * workspace >= sdd_smooth_interfaces_workspace_bytes(L). */
+size_t sdd_smooth_interfaces_workspace_bytes(const sdd_layout* L);
+
+sdd_status sdd_smooth_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t span, double* vert, double* horiz,
+                                 void* workspace, size_t ws_bytes, void* stream);
+
 /* -------------------------------------------------------------- serving ---
  * A request server that batches whole mesh requests (interface estimate,
  * fill and subdomain solves) continuously: requests that arrive while

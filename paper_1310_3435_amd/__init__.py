@@ -113,6 +113,20 @@ def lib() -> C.CDLL:
     L.sdd_subdomain_solve.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), C.POINTER(sdd_layout), P, P,
                                       D, I32, P, P, P, P, SZ, P]
     L.sdd_subdomain_solve.restype = C.c_int
+    L.sdd_quality_workspace_bytes.argtypes = [I32, I32]
+    L.sdd_quality_workspace_bytes.restype = SZ
+    L.sdd_mesh_quality.argtypes = [P, I32, I32, P, P, P, P, SZ, P]
+    L.sdd_mesh_quality.restype = C.c_int
+    L.sdd_mesh_compare.argtypes = [P, I32, I32, C.POINTER(sdd_density), P, P, P, P, SZ, P]
+    L.sdd_mesh_compare.restype = C.c_int
+    L.sdd_smooth_workspace_bytes.argtypes = [C.POINTER(sdd_layout)]
+    L.sdd_smooth_workspace_bytes.restype = SZ
+    L.sdd_mesh_smooth.argtypes = [P, C.POINTER(sdd_layout), I32, D, D, I32, P, P, SZ, P]
+    L.sdd_mesh_smooth.restype = C.c_int
+    L.sdd_smooth_interfaces_workspace_bytes.argtypes = [C.POINTER(sdd_layout)]
+    L.sdd_smooth_interfaces_workspace_bytes.restype = SZ
+    L.sdd_smooth_interfaces.argtypes = [P, C.POINTER(sdd_layout), I32, P, P, P, SZ, P]
+    L.sdd_smooth_interfaces.restype = C.c_int
     L.sdd_server_create.argtypes = [P, SZ, I32, I64, I64, I64, C.POINTER(P)]
     L.sdd_server_create.restype = C.c_int
     L.sdd_server_submit.argtypes = [P, C.POINTER(sdd_request), P, C.POINTER(C.c_uint64)]
@@ -135,7 +149,9 @@ EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd
            "sdd_interface_estimate", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
            "sdd_fill_interfaces", "sdd_subdomain_workspace_bytes", "sdd_subdomain_solve", "sdd_server_create",
            "sdd_server_submit", "sdd_server_poll", "sdd_server_wait", "sdd_server_cancel", "sdd_server_clock",
-           "sdd_server_destroy"]
+           "sdd_server_destroy", "sdd_quality_workspace_bytes", "sdd_mesh_quality", "sdd_mesh_compare",
+           "sdd_smooth_workspace_bytes", "sdd_mesh_smooth", "sdd_smooth_interfaces_workspace_bytes",
+           "sdd_smooth_interfaces"]
 
 
 def _check(rc: int, what: str):
@@ -377,10 +393,64 @@ def sdd_subdomain_solve(ctx: Context, density: dict, bmap, layout: dict, vert, h
     return {"mesh": mesh, "sweeps": sweeps, "resid": resid, "_ws": ws}
 
 
+# ------------------------------------------------ quality and smoothing
+
+def sdd_mesh_quality(ctx: Context, mesh, want_cells: bool = False, stream=None) -> dict:
+    """Q of every cell (eq. (11)) and {Q_max, Q_mean, folded} as device
+    tensors: 'out' float64 [3], 'q' [ny-1, nx-1] if want_cells."""
+    torch = _torch()
+    ny, nx = int(mesh.shape[0]), int(mesh.shape[1])
+    dev = mesh.device
+    out = torch.empty(3, dtype=torch.float64, device=dev)
+    q = torch.empty((ny - 1, nx - 1), dtype=torch.float64, device=dev) if want_cells else None
+    ws = ctx.workspace(int(lib().sdd_quality_workspace_bytes(nx, ny)))
+    _check(lib().sdd_mesh_quality(ctx.h, nx, ny, _ptr(mesh), _ptr(q), _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream(stream)), "sdd_mesh_quality")
+    return {"out": out, "q": q}
+
+
+def sdd_mesh_compare(ctx: Context, density: dict, mesh, ref, stream=None):
+    """Device float64 [2]: l_inf of the density at the nodes, largest node
+    displacement."""
+    torch = _torch()
+    ny, nx = int(mesh.shape[0]), int(mesh.shape[1])
+    out = torch.empty(2, dtype=torch.float64, device=mesh.device)
+    D = make_density(density)
+    ws = ctx.workspace(int(lib().sdd_quality_workspace_bytes(nx, ny)))
+    _check(lib().sdd_mesh_compare(ctx.h, nx, ny, C.byref(D), _ptr(mesh), _ptr(ref), _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "sdd_mesh_compare")
+    return out
+
+
+def sdd_mesh_smooth(ctx: Context, layout: dict, mesh, dt: float, k: float, steps: int, per_subdomain: bool = True,
+                    stream=None):
+    """Perona-Malik FTCS smoothing of the device mesh [ny, nx, 2] in place (eq. (12))."""
+    torch = _torch()
+    L = make_layout(layout)
+    ws = torch.empty(int(lib().sdd_smooth_workspace_bytes(C.byref(L))), dtype=torch.uint8, device=mesh.device)
+    _check(lib().sdd_mesh_smooth(ctx.h, C.byref(L), 1 if per_subdomain else 0, float(dt), float(k), int(steps),
+                                 _ptr(mesh), _ptr(ws), ws.numel(), _stream(stream)), "sdd_mesh_smooth")
+    return mesh
+
+
+def sdd_smooth_interfaces(ctx: Context, layout: dict, vert, horiz, span: int, stream=None):
+    """Local quadratic regression of the device interface lines in place (Sec. 4)."""
+    torch = _torch()
+    L = make_layout(layout)
+    ws = torch.empty(max(int(lib().sdd_smooth_interfaces_workspace_bytes(C.byref(L))), 256), dtype=torch.uint8,
+                     device=f"cuda:{ctx.device}")
+    _check(lib().sdd_smooth_interfaces(ctx.h, C.byref(L), int(span),
+                                       _ptr(vert) if vert is not None and vert.numel() else None,
+                                       _ptr(horiz) if horiz is not None and horiz.numel() else None,
+                                       _ptr(ws), ws.numel(), _stream(stream)), "sdd_smooth_interfaces")
+    return vert, horiz
+
+
 # ------------------------------------------------------------ pipeline
 
 def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -> dict:
-    """Nodes -> interface estimate -> fill -> subdomain solves, all on the GPU."""
+    """Nodes -> interface estimate -> fill [-> interface smoothing] ->
+    subdomain solves [-> Perona-Malik smoothing], all on the GPU."""
     dens = cfg["density"]
     B = Bmap(cfg["bmap"], ctx, dens)
     L = cfg["layout"]
@@ -389,7 +459,13 @@ def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -
                                  per_path=per_path, stream=stream, exit_test=cfg.get("exit_test", "step"))
     vert, horiz = sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"),
                                       stream=stream)
+    if cfg.get("smooth_span", 0) > 0:
+        sdd_smooth_interfaces(ctx, L, vert, horiz, int(cfg["smooth_span"]), stream=stream)
     sol = sdd_subdomain_solve(ctx, dens, B, L, vert, horiz, stream=stream)
+    pm = cfg.get("pm")
+    if pm:
+        sdd_mesh_smooth(ctx, L, sol["mesh"], pm["dt"], pm["k"], pm["steps"], pm.get("per_subdomain", True),
+                        stream=stream)
     return {"nodes": nodes, "est": est, "vert": vert, "horiz": horiz, "mesh": sol["mesh"], "sweeps": sol["sweeps"],
             "resid": sol["resid"], "_keep": (B, sol)}
 

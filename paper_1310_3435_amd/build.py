@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "walk.hip", "mesh.hip", "serve.hip"]
+SOURCES = ["api.hip", "walk.hip", "mesh.hip", "serve.hip", "postprocess.hip"]
 LIB = os.path.join(HERE, "libsdd.so")
 ARCH = os.environ.get("SDD_OFFLOAD_ARCH", "gfx950")
 

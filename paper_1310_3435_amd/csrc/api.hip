@@ -198,4 +198,76 @@ sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bma
                                            sweeps, resid, workspace, (hipStream_t)stream));
 }
 
+// ------------------------------------------------------ quality, smoothing
+
+size_t sdd_quality_workspace_bytes(int32_t nx, int32_t ny)
+{
+    if (nx < 2 || ny < 2) return 0;
+    return post_workspace_bytes();
+}
+
+sdd_status sdd_mesh_quality(sdd_ctx* ctx, int32_t nx, int32_t ny, const double* mesh, double* q, double* out,
+                            void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx || !mesh || !out || !workspace || nx < 2 || ny < 2) return SDD_EINVAL;
+    if ((int64_t)nx * ny > ((int64_t)1 << 31)) return SDD_EINVAL;
+    if (ws_bytes < post_workspace_bytes()) return SDD_ENOSPC;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_quality(nx, ny, mesh, q, out, workspace, (hipStream_t)stream));
+}
+
+sdd_status sdd_mesh_compare(sdd_ctx* ctx, int32_t nx, int32_t ny, const sdd_density* w, const double* mesh,
+                            const double* ref, double* out, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx || !mesh || !ref || !out || !workspace || nx < 2 || ny < 2) return SDD_EINVAL;
+    if ((int64_t)nx * ny > ((int64_t)1 << 31)) return SDD_EINVAL;
+    sdd_status s = check_density(w);
+    if (s != SDD_OK) return s;
+    if (ws_bytes < post_workspace_bytes()) return SDD_ENOSPC;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_compare(nx, ny, to_device(w), mesh, ref, out, workspace, (hipStream_t)stream));
+}
+
+size_t sdd_smooth_workspace_bytes(const sdd_layout* L)
+{
+    if (check_layout(L) != SDD_OK) return 0;
+    return (size_t)L->nx * L->ny * 2 * sizeof(double);
+}
+
+sdd_status sdd_mesh_smooth(sdd_ctx* ctx, const sdd_layout* L, int32_t per_subdomain, double dt, double k,
+                           int32_t steps, double* mesh, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx || !mesh || !workspace) return SDD_EINVAL;
+    sdd_status s = check_layout(L);
+    if (s != SDD_OK) return s;
+    if (per_subdomain != 0 && per_subdomain != 1) return SDD_EINVAL;
+    if (!(dt > 0.0) || !(k > 0.0) || !is_finite(k) || steps < 0) return SDD_EINVAL;
+    const double hx2 = (double)(L->nx - 1) * (L->nx - 1), hy2 = (double)(L->ny - 1) * (L->ny - 1);
+    if (!(dt * (2.0 * hx2 + 2.0 * hy2) <= 1.0)) return SDD_EINVAL;  // FTCS stability
+    if (ws_bytes < sdd_smooth_workspace_bytes(L)) return SDD_ENOSPC;
+    if (steps == 0) return SDD_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_smooth(*L, per_subdomain, dt, k, steps, mesh, workspace, (hipStream_t)stream));
+}
+
+size_t sdd_smooth_interfaces_workspace_bytes(const sdd_layout* L)
+{
+    if (check_layout(L) != SDD_OK) return 0;
+    return smooth_interfaces_workspace_bytes(*L);
+}
+
+sdd_status sdd_smooth_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t span, double* vert, double* horiz,
+                                 void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ctx || !workspace) return SDD_EINVAL;
+    sdd_status s = check_layout(L);
+    if (s != SDD_OK) return s;
+    if (span < 5 || (span & 1) == 0) return SDD_EINVAL;
+    if (L->sx > 1 && (!vert || span > L->ny)) return SDD_EINVAL;
+    if (L->sy > 1 && (!horiz || span > L->nx)) return SDD_EINVAL;
+    if (ws_bytes < smooth_interfaces_workspace_bytes(*L)) return SDD_ENOSPC;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_smooth_interfaces(*L, span, vert, horiz, workspace, (hipStream_t)stream));
+}
+
 }  // extern "C"

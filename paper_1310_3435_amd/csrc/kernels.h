@@ -59,4 +59,15 @@ hipError_t launch_subdomain_solve(const Density& D, const Bmap& B, const sdd_lay
                                   double* resid, void* workspace, hipStream_t stream);
 size_t subdomain_workspace_bytes(const sdd_layout& L);
 
+// postprocess.hip
+size_t post_workspace_bytes();
+hipError_t launch_quality(int nx, int ny, const double* mesh, double* q, double* out, void* ws, hipStream_t stream);
+hipError_t launch_compare(int nx, int ny, const Density& D, const double* mesh, const double* ref, double* out,
+                          void* ws, hipStream_t stream);
+hipError_t launch_smooth(const sdd_layout& L, int per_subdomain, double dt, double k, int steps, double* mesh,
+                         void* ws, hipStream_t stream);
+hipError_t launch_smooth_interfaces(const sdd_layout& L, int span, double* vert, double* horiz, void* ws,
+                                    hipStream_t stream);
+size_t smooth_interfaces_workspace_bytes(const sdd_layout& L);
+
 }  // namespace sdd
