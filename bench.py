@@ -260,6 +260,119 @@ def bridge_legs(ctx, cfg, B, nodes, plain_walk_ms: float, plain_steps: int, plai
     return out
 
 
+def quality_study(ctx, cfg, B, nodes, est_mean, dd_mesh):
+    """Mesh quality of the domain-decomposition mesh against the single-domain
+    finite-difference mesh of the same grid (Sec. 3.1-3.3: Q_max, Q_mean,
+    R = Q/Q^S, l_inf), with Perona-Malik smoothing of both (Sec. 3.4, eq. (12);
+    dt/h^2 as in the paper's 29 x 29 example, k = 1000) and interface
+    pre-smoothing (Sec. 4).  Kernel times from HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    dens, L = cfg["density"], cfg["layout"]
+    nx, ny = L["nx"], L["ny"]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        r = fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return r, a.elapsed_time(b)
+
+    single = {"nx": nx, "ny": ny, "sx": 1, "sy": 1}
+    ref_sol, ref_ms = timed(lambda: sdd.sdd_subdomain_solve(ctx, dens, B, single, None, None))
+    ref = ref_sol["mesh"]
+
+    def q(m):
+        return sdd.sdd_mesh_quality(ctx, m)["out"].cpu().numpy()
+
+    def row(m_dd, m_ref):
+        qd, qr = q(m_dd), q(m_ref)
+        cmp = sdd.sdd_mesh_compare(ctx, dens, m_dd, m_ref).cpu().numpy()
+        return {"q_max": float(qr[0]), "q_mean": float(qr[1]), "q_max_dd": float(qd[0]), "q_mean_dd": float(qd[1]),
+                "r_max": float(qr[0] / qd[0]), "r_mean": float(qr[1] / qd[1]), "linf": float(cmp[0]),
+                "max_disp": float(cmp[1]), "folded_dd": int(qd[2])}
+
+    _, q_ms = timed(lambda: sdd.sdd_mesh_quality(ctx, dd_mesh))
+    out = {"reference": f"single-domain finite-difference solve {nx}x{ny} (SOR, {int(ref_sol['sweeps'].max())} "
+                        f"sweeps, {ref_ms:.1f} ms)",
+           "quality_kernel_ms": q_ms, "no_smoothing": row(dd_mesh, ref)}
+    dt = 1e-4 * 28**2 / ((nx - 1) ** 2)          # the paper's dt / h^2 on its 29 x 29 grid
+    sm = {}
+    for m in (1, 2, 5, 10):
+        a, b = dd_mesh.clone(), ref.clone()
+        _, ms = timed(lambda: sdd.sdd_mesh_smooth(ctx, L, a, dt, 1000.0, m, per_subdomain=True))
+        sdd.sdd_mesh_smooth(ctx, single, b, dt, 1000.0, m, per_subdomain=False)
+        sm[str(m)] = dict(row(a, b), smooth_ms=ms)
+    out["perona_malik_per_subdomain"] = {"dt": dt, "k": 1000.0, "steps": sm}
+    vert, horiz = sdd.sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est_mean, cfg.get("interp", "linear"))
+    _, ls_ms = timed(lambda: sdd.sdd_smooth_interfaces(ctx, L, vert, horiz, 9))
+    sol = sdd.sdd_subdomain_solve(ctx, dens, B, L, vert, horiz)
+    out["interface_presmoothing_span9"] = dict(row(sol["mesh"], ref), smooth_ms=ls_ms)
+    return out
+
+
+def paper_study(ctx):
+    """The kinds of study of the paper's Sec. 3 on a workload shaped like its
+    running example (29 x 29 grid, Gaussian monitor function, four square
+    subdomains): the mesh by Monte Carlo at every node with N = 1e3 and 1e4
+    (Table 1: l_inf, Q^S_max, Q^S_mean, R_max, R_mean), Perona-Malik
+    smoothing of the N = 1e3 mesh and of the reference for m = 1, 2, 5, 10
+    steps with dt = 1e-4, k = 1000 (Table 2), the decomposition with every
+    interface node by Monte Carlo (Sec. 3.5) and with seven equidistant
+    points per dividing line and linear fill (Sec. 3.6).  Reference: the
+    single-domain finite-difference mesh."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    import workloads
+
+    cfg = workloads.cfg_paper_example()
+    dens, L = cfg["density"], cfg["layout"]
+    nx, ny = L["nx"], L["ny"]
+    single = {"nx": nx, "ny": ny, "sx": 1, "sy": 1}
+    B = sdd.Bmap(cfg["bmap"], ctx, dens)
+    ref = sdd.sdd_subdomain_solve(ctx, dens, B, single, None, None)["mesh"]
+
+    def row(m, r):
+        qs = sdd.sdd_mesh_quality(ctx, m)["out"].cpu().numpy()
+        qr = sdd.sdd_mesh_quality(ctx, r)["out"].cpu().numpy()
+        c = sdd.sdd_mesh_compare(ctx, dens, m, r).cpu().numpy()
+        return {"linf": float(c[0]), "q_max": float(qr[0]), "q_mean": float(qr[1]), "q_max_s": float(qs[0]),
+                "q_mean_s": float(qs[1]), "r_max": float(qr[0] / qs[0]), "r_mean": float(qr[1] / qs[1]),
+                "folded": int(qs[2])}
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3
+
+    out = {"workload": f"{cfg['name']}: {nx}x{ny}, 2x2 subdomains, bridge exits at dt {cfg['dt']:g}, float walks",
+           "whole_grid": {}, "smoothing_n1000": {}, "decomposition": {}}
+    prob = {}
+    for n in (1000, 10000):
+        r, ms = timed(lambda: sdd.run_probabilistic(ctx, dict(cfg, paths=n)))
+        prob[n] = r["mesh"]
+        out["whole_grid"][str(n)] = dict(row(r["mesh"], ref), ms=ms, nodes=int(r["nodes"].shape[0]))
+    for m in (1, 2, 5, 10):
+        a, b = prob[1000].clone(), ref.clone()
+        sdd.sdd_mesh_smooth(ctx, single, a, 1e-4, 1000.0, m, per_subdomain=False)
+        sdd.sdd_mesh_smooth(ctx, single, b, 1e-4, 1000.0, m, per_subdomain=False)
+        out["smoothing_n1000"][str(m)] = row(a, b)
+    r, ms = timed(lambda: sdd.run_pipeline(ctx, cfg))
+    out["decomposition"]["all_interface_nodes"] = dict(row(r["mesh"], ref), ms=ms,
+                                                       nodes=int(r["nodes"].shape[0]))
+    r, ms = timed(lambda: sdd.run_pipeline(ctx, dict(cfg, k=3)))
+    out["decomposition"]["seven_points_per_line"] = dict(row(r["mesh"], ref), ms=ms,
+                                                         nodes=int(r["nodes"].shape[0]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +393,7 @@ def main():
     ap.add_argument("--sweep-paths", type=int, default=1000000)
     ap.add_argument("--sweep-dts", default="1e-3,1e-4,1e-5,1e-6")
     ap.add_argument("--sweep-exit", default="step,bridge", help="exit tests of the sweep")
+    ap.add_argument("--no-quality", action="store_true", help="skip the mesh-quality study")
     ap.add_argument("--bridge-paths", type=int, default=1000000,
                     help="paths per node of the equal-bias comparison (0: skip the bridge legs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -421,6 +535,9 @@ def main():
                              "fp32_speedup_at_equal_se": ms64 / float(np.mean(walk_ms)),
                              "max_node_diff_fp32_vs_fp64": float(np.abs(e64["mean"].cpu().numpy() -
                                                                         est["mean"].cpu().numpy()).max())}
+    if not args.no_quality:
+        line["quality"] = quality_study(ctx, cfg, B, nodes, est["mean"], sol["mesh"])
+        line["paper_example"] = paper_study(ctx)
     if args.bridge_paths > 0:
         line["bridge"] = bridge_legs(ctx, cfg, B, nodes, float(np.mean(walk_ms)), steps_per_pass,
                                      est["mean"].cpu().numpy(), args.bridge_paths)

@@ -267,6 +267,19 @@ sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bma
                                double* mesh, int32_t* sweeps, double* resid, void* workspace, size_t ws_bytes,
                                void* stream);
 
+/* ------------------------------------------------------ whole-grid mesh ---
+ * The mesh by Monte Carlo at every grid point (Sec. 3.3), for comparison
+ * with the decomposition.  sdd_grid_nodes writes the (nx-2)(ny-2) interior
+ * nodes (i/(nx-1), j/(ny-1)) row by row (j = 1..ny-2 outer, i = 1..nx-2
+ * inner) to device nodes[][2]; estimate them with sdd_interface_estimate;
+ * sdd_assemble_mesh then writes device mesh[ny][nx][2]: the boundary map on
+ * the ring (as sdd_subdomain_solve writes it) and device values[][2], in
+ * the order of sdd_grid_nodes, inside.  nx, ny >= 3. */
+sdd_status sdd_grid_nodes(sdd_ctx* ctx, int32_t nx, int32_t ny, double* nodes, void* stream);
+
+sdd_status sdd_assemble_mesh(sdd_ctx* ctx, int32_t nx, int32_t ny, const sdd_bmap* bmap, const double* values,
+                             double* mesh, void* stream);
+
 /* ------------------------------------------------- quality and smoothing ---
  * Geometric mesh quality (eq. (11), Sec. 3.1).  For each of the
  * (nx-1)(ny-1) cells, J is the Jacobian of the cell's bilinear map at its

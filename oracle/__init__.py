@@ -22,6 +22,8 @@ Parts (Bihlo & Haynes, arXiv 1310.3435):
   subdomain by centred finite differences (Sec. 2.1, Sec. 3.2), here solved
   directly by a sparse LU rather than iterated, so that it is the exact
   discrete solution.
+* ``grid_nodes``, ``assemble_mesh``, ``probabilistic_mesh`` -- the mesh by
+  Monte Carlo at every grid point (Sec. 3.3).
 * ``mesh_quality``, ``mesh_compare``, ``perona_malik``,
   ``smooth_interfaces`` -- quality measure and smoothing (``postprocess.py``).
 
@@ -574,6 +576,41 @@ def global_solve(density: dict, bmap, nx: int, ny: int) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ pipeline
+
+def grid_nodes(nx: int, ny: int) -> np.ndarray:
+    """Every interior node of the nx x ny grid, row by row (eta outer, xi
+    inner): the node set of a mesh computed by Monte Carlo at every grid point
+    (Sec. 3.3)."""
+    i = np.arange(1, nx - 1)
+    j = np.arange(1, ny - 1)
+    xi = i / (nx - 1)
+    eta = j / (ny - 1)
+    return np.stack([np.tile(xi, ny - 2), np.repeat(eta, nx - 2)], 1)
+
+
+def assemble_mesh(bmap, nx: int, ny: int, values: np.ndarray) -> np.ndarray:
+    """mesh[ny][nx][2]: the boundary map on the ring, `values` (in the order
+    of grid_nodes) inside."""
+    mesh = boundary_frame(bmap, nx, ny)
+    mesh[1:-1, 1:-1] = np.asarray(values, dtype=np.float64).reshape(ny - 2, nx - 2, 2)
+    return mesh
+
+
+def probabilistic_mesh(cfg: dict, nthreads: int = 0) -> dict:
+    """The whole mesh by Monte Carlo at every interior node (Sec. 3.3), with
+    optional Perona-Malik smoothing over the whole grid (Sec. 3.4)."""
+    dens = cfg["density"]
+    B = Bmap(cfg["bmap"], dens)
+    nx, ny = cfg["layout"]["nx"], cfg["layout"]["ny"]
+    nodes = grid_nodes(nx, ny)
+    est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
+                             nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge")
+    mesh = assemble_mesh(B, nx, ny, est["mean"])
+    pm = cfg.get("pm")
+    if pm:
+        mesh = perona_malik(mesh, pm["dt"], pm["k"], pm["steps"])
+    return {"nodes": nodes, "est": est, "mesh": mesh}
+
 
 def pipeline(cfg: dict, nthreads: int = 0) -> dict:
     """Nodes -> interface estimate -> fill [-> interface smoothing] ->

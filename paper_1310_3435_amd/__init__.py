@@ -113,6 +113,10 @@ def lib() -> C.CDLL:
     L.sdd_subdomain_solve.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), C.POINTER(sdd_layout), P, P,
                                       D, I32, P, P, P, P, SZ, P]
     L.sdd_subdomain_solve.restype = C.c_int
+    L.sdd_grid_nodes.argtypes = [P, I32, I32, P, P]
+    L.sdd_grid_nodes.restype = C.c_int
+    L.sdd_assemble_mesh.argtypes = [P, I32, I32, C.POINTER(sdd_bmap), P, P, P]
+    L.sdd_assemble_mesh.restype = C.c_int
     L.sdd_quality_workspace_bytes.argtypes = [I32, I32]
     L.sdd_quality_workspace_bytes.restype = SZ
     L.sdd_mesh_quality.argtypes = [P, I32, I32, P, P, P, P, SZ, P]
@@ -151,7 +155,7 @@ EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd
            "sdd_server_submit", "sdd_server_poll", "sdd_server_wait", "sdd_server_cancel", "sdd_server_clock",
            "sdd_server_destroy", "sdd_quality_workspace_bytes", "sdd_mesh_quality", "sdd_mesh_compare",
            "sdd_smooth_workspace_bytes", "sdd_mesh_smooth", "sdd_smooth_interfaces_workspace_bytes",
-           "sdd_smooth_interfaces"]
+           "sdd_smooth_interfaces", "sdd_grid_nodes", "sdd_assemble_mesh"]
 
 
 def _check(rc: int, what: str):
@@ -391,6 +395,42 @@ def sdd_subdomain_solve(ctx: Context, density: dict, bmap, layout: dict, vert, h
                                    ws.numel(), _stream(stream))
     _check(rc, "sdd_subdomain_solve")
     return {"mesh": mesh, "sweeps": sweeps, "resid": resid, "_ws": ws}
+
+
+# ------------------------------------------------------ whole-grid mesh
+
+def sdd_grid_nodes(ctx: Context, nx: int, ny: int, stream=None):
+    """Device float64 [(nx-2)(ny-2), 2]: every interior grid node, row by row."""
+    torch = _torch()
+    nodes = torch.empty(((nx - 2) * (ny - 2), 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(lib().sdd_grid_nodes(ctx.h, int(nx), int(ny), _ptr(nodes), _stream(stream)), "sdd_grid_nodes")
+    return nodes
+
+
+def sdd_assemble_mesh(ctx: Context, nx: int, ny: int, bmap: "Bmap", values, stream=None):
+    """Device mesh [ny, nx, 2]: boundary map on the ring, values inside."""
+    torch = _torch()
+    mesh = torch.empty((ny, nx, 2), dtype=torch.float64, device=values.device)
+    _check(lib().sdd_assemble_mesh(ctx.h, int(nx), int(ny), C.byref(bmap.s), _ptr(values), _ptr(mesh),
+                                   _stream(stream)), "sdd_assemble_mesh")
+    return mesh
+
+
+def run_probabilistic(ctx: Context, cfg: dict, stream=None) -> dict:
+    """The whole mesh by Monte Carlo at every interior node (Sec. 3.3) [->
+    Perona-Malik smoothing of the whole grid (Sec. 3.4)], all on the GPU."""
+    dens = cfg["density"]
+    B = Bmap(cfg["bmap"], ctx, dens)
+    nx, ny = cfg["layout"]["nx"], cfg["layout"]["ny"]
+    nodes = sdd_grid_nodes(ctx, nx, ny, stream=stream)
+    est = sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
+                                 stream=stream, exit_test=cfg.get("exit_test", "step"))
+    mesh = sdd_assemble_mesh(ctx, nx, ny, B, est["mean"], stream=stream)
+    pm = cfg.get("pm")
+    if pm:
+        sdd_mesh_smooth(ctx, {"nx": nx, "ny": ny, "sx": 1, "sy": 1}, mesh, pm["dt"], pm["k"], pm["steps"], False,
+                        stream=stream)
+    return {"nodes": nodes, "est": est, "mesh": mesh, "_keep": B}
 
 
 # ------------------------------------------------ quality and smoothing

@@ -198,6 +198,27 @@ sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bma
                                            sweeps, resid, workspace, (hipStream_t)stream));
 }
 
+// ---------------------------------------------------- whole-grid node set
+
+sdd_status sdd_grid_nodes(sdd_ctx* ctx, int32_t nx, int32_t ny, double* nodes, void* stream)
+{
+    if (!ctx || nx < 3 || ny < 3 || !nodes) return SDD_EINVAL;
+    if ((int64_t)nx * ny > ((int64_t)1 << 31)) return SDD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_grid_nodes(nx, ny, nodes, (hipStream_t)stream));
+}
+
+sdd_status sdd_assemble_mesh(sdd_ctx* ctx, int32_t nx, int32_t ny, const sdd_bmap* bmap, const double* values,
+                             double* mesh, void* stream)
+{
+    if (!ctx || nx < 3 || ny < 3 || !values || !mesh) return SDD_EINVAL;
+    if ((int64_t)nx * ny > ((int64_t)1 << 31)) return SDD_EINVAL;
+    sdd_status s = check_bmap(bmap);
+    if (s != SDD_OK) return s;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_assemble(nx, ny, to_device(bmap), values, mesh, (hipStream_t)stream));
+}
+
 // ------------------------------------------------------ quality, smoothing
 
 size_t sdd_quality_workspace_bytes(int32_t nx, int32_t ny)

@@ -58,6 +58,8 @@ hipError_t launch_subdomain_solve(const Density& D, const Bmap& B, const sdd_lay
                                   const double* horiz, double tol, int max_sweeps, double* mesh, int32_t* sweeps,
                                   double* resid, void* workspace, hipStream_t stream);
 size_t subdomain_workspace_bytes(const sdd_layout& L);
+hipError_t launch_grid_nodes(int nx, int ny, double* nodes, hipStream_t stream);
+hipError_t launch_assemble(int nx, int ny, const Bmap& B, const double* values, double* mesh, hipStream_t stream);
 
 // postprocess.hip
 size_t post_workspace_bytes();

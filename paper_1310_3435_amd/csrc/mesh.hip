@@ -390,6 +390,53 @@ __global__ __launch_bounds__(256) void frame_kernel(sdd_layout L, const Bmap B, 
     }
 }
 
+// Every interior node of the grid, row by row (Sec. 3.3: Monte Carlo at
+// every grid point).
+__global__ __launch_bounds__(256) void grid_nodes_kernel(int nx, int ny, double* __restrict__ nodes)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int w = nx - 2;
+    if (id >= (int64_t)w * (ny - 2)) return;
+    const int i = 1 + (int)(id % w), j = 1 + (int)(id / w);
+    nodes[2 * id] = (double)i / (nx - 1);
+    nodes[2 * id + 1] = (double)j / (ny - 1);
+}
+
+// Boundary ring from the map, interior from per-node estimates in the
+// order of grid_nodes_kernel.
+__global__ __launch_bounds__(256) void assemble_kernel(int nx, int ny, const Bmap B, const double* __restrict__ values,
+                                                       double* __restrict__ mesh)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)nx * ny) return;
+    const int i = (int)(id % nx), j = (int)(id / nx);
+    double* o = mesh + 2 * id;
+    if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1) {
+        const double xi = (double)i / (nx - 1), eta = (double)j / (ny - 1);
+        bmap_eval(B, boundary_side(xi, eta), xi, eta, o[0], o[1]);
+    } else {
+        const double* v = values + 2 * ((int64_t)(j - 1) * (nx - 2) + (i - 1));
+        o[0] = v[0];
+        o[1] = v[1];
+    }
+}
+
+hipError_t launch_grid_nodes(int nx, int ny, double* nodes, hipStream_t stream)
+{
+    const int64_t n = (int64_t)(nx - 2) * (ny - 2);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(grid_nodes_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, nx, ny, nodes);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(int nx, int ny, const Bmap& B, const double* values, double* mesh, hipStream_t stream)
+{
+    const int64_t n = (int64_t)nx * ny;
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, nx, ny, B, values,
+                       mesh);
+    return hipGetLastError();
+}
+
 // Initial guess for every subdomain interior: the transfinite (Coons)
 // interpolant of the subdomain's four sides.
 __global__ __launch_bounds__(256) void coons_kernel(sdd_layout L, double* __restrict__ mesh)

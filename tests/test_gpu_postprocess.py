@@ -9,7 +9,6 @@
   Cramer's rule against the oracle's least-squares solver);
 * the smoothed pipeline end to end against the oracle's.
 """
-import ctypes as C
 
 import numpy as np
 import pytest
@@ -159,3 +158,22 @@ def test_smoothed_pipeline_matches_oracle(ctx, ref):
     assert d <= 1e-9
     q = sdd.sdd_mesh_quality(ctx, g["mesh"])["out"].cpu().numpy()
     assert q[0] == pytest.approx(ref.mesh_quality(r["mesh"])["q_max"], rel=1e-9)
+
+
+def test_whole_grid_mesh_matches_oracle(ctx, ref):
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    g = sdd.sdd_grid_nodes(ctx, 29, 23).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(g, ref.grid_nodes(29, 23))
+    c = dict(W.cfg_paper_example(), paths=500, prec="fp64",
+             pm={"dt": 1e-4, "k": 1000.0, "steps": 5})
+    say("whole-grid Monte Carlo mesh, 29 x 29, fp64, smoothed")
+    out = sdd.run_probabilistic(ctx, c)
+    mesh = out["mesh"].cpu().numpy()
+    torch.cuda.synchronize()
+    r = ref.probabilistic_mesh(c)
+    d = np.abs(mesh - r["mesh"]).max()
+    say(f"whole-grid mesh vs oracle: max diff {d:.3e}")
+    assert d <= 1e-10

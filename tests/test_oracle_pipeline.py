@@ -207,3 +207,33 @@ def test_pipeline_small_workload_gives_a_valid_mesh(ref):
     # and lies within MC error of the brute-force solution on the same grid
     g = ref.global_solve(c["density"], ref.Bmap(c["bmap"]), 65, 33)
     assert np.max(np.abs(mesh - g)) < 0.05
+
+
+def test_grid_nodes_and_assembly(ref):
+    nodes = ref.grid_nodes(6, 5)
+    assert nodes.shape == (4 * 3, 2)
+    # row by row: eta outer, xi inner, interior only
+    assert np.array_equal(nodes[:4, 0], np.arange(1, 5) / 5) and np.all(nodes[:4, 1] == 1 / 4)
+    assert np.array_equal(nodes[4:8, 1], np.full(4, 2 / 4))
+    B = ref.Bmap({"kind": "annulus", "p": [1.0, 2.0, 0.0, 0.5 * math.pi]})
+    vals = np.arange(24, dtype=float).reshape(12, 2)
+    mesh = ref.assemble_mesh(B, 6, 5, vals)
+    frame = ref.boundary_frame(B, 6, 5)
+    ring = np.ones((5, 6), dtype=bool)
+    ring[1:-1, 1:-1] = False
+    assert np.array_equal(mesh[ring], frame[ring])
+    assert np.array_equal(mesh[1:-1, 1:-1].reshape(-1, 2), vals)
+
+
+def test_whole_grid_mesh_of_constant_density_is_the_identity(ref):
+    # w = 1 and the identity map: x = xi, y = eta exactly; the bridge walk's
+    # bias is O(dt), so the Monte Carlo mesh is within 4 SE + 4 dt of the grid
+    cfg = {"density": {"base": 1.0, "terms": []}, "bmap": {"kind": "identity"},
+           "layout": {"nx": 9, "ny": 7, "sx": 1, "sy": 1}, "paths": 4000, "dt": 1e-4, "seed": 3,
+           "exit_test": "bridge"}
+    r = ref.probabilistic_mesh(cfg)
+    exact = ref.grid_nodes(9, 7)
+    err = np.abs(r["est"]["mean"] - exact)
+    assert np.all(err <= 4 * r["est"]["se"] + 4e-4)
+    m = r["mesh"]
+    assert np.allclose(m[0, :, 0], np.arange(9) / 8) and np.allclose(m[:, 0, 1], np.arange(7) / 6)

@@ -157,9 +157,25 @@ def random_density(seed: int, n_terms: int = 3) -> dict:
     return density(rng.uniform(0.5, 2.0), terms)
 
 
+def cfg_paper_example() -> dict:
+    """The shape of the paper's running example (Sec. 3, its Gaussian monitor
+    function with R = 15): w = 1 + 15 exp(-1/2) exp(-50 |(xi, eta) - (3/4, 1/2)|^2)
+    on a 29 x 29 grid in four square subdomains, every interface node by
+    Monte Carlo (Sec. 3.5) with N = 1e4; Brownian-bridge exits at dt = 1e-4."""
+    return {
+        "name": "paper_example_29",
+        "density": density(1.0, [_term("gauss", 15.0 * math.exp(-0.5), 50.0, 0.75, 0.5)]),
+        "bmap": {"kind": "identity"},
+        "layout": {"nx": 29, "ny": 29, "sx": 2, "sy": 2},
+        "k": 13, "placement": "uniform", "interp": "linear",
+        "paths": 10000, "dt": 1e-4, "exit_test": "bridge", "seed": 6, "prec": "fp32",
+    }
+
+
 CONFIGS: Dict[str, callable] = {
     "plain_fp64_gauss": cfg_plain_fp64,
     "ring_fp32_4x4x65": cfg_ring_fp32,
     "annulus_fp32_8x8x129": cfg_annulus_fp32,
     "sin2_bias_sweep": cfg_sin2_sweep,
+    "paper_example_29": cfg_paper_example,
 }
