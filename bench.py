@@ -322,9 +322,10 @@ def paper_study(ctx):
     (Table 1: l_inf, Q^S_max, Q^S_mean, R_max, R_mean), Perona-Malik
     smoothing of the N = 1e3 mesh and of the reference for m = 1, 2, 5, 10
     steps with dt = 1e-4, k = 1000 (Table 2), the decomposition with every
-    interface node by Monte Carlo (Sec. 3.5) and with seven equidistant
-    points per dividing line and linear fill (Sec. 3.6).  Reference: the
-    single-domain finite-difference mesh."""
+    interface node by Monte Carlo (Sec. 3.5), with seven equidistant
+    points per dividing line and with points at the extrema of w_s and w_ss
+    (Sec. 3.6), linear fill.  Reference: the single-domain
+    finite-difference mesh."""
     import torch
 
     import paper_1310_3435_amd as sdd
@@ -370,6 +371,10 @@ def paper_study(ctx):
     r, ms = timed(lambda: sdd.run_pipeline(ctx, dict(cfg, k=3)))
     out["decomposition"]["seven_points_per_line"] = dict(row(r["mesh"], ref), ms=ms,
                                                          nodes=int(r["nodes"].shape[0]))
+    r, ms = timed(lambda: sdd.run_pipeline(ctx, dict(cfg, k=8, placement="extrema")))
+    out["decomposition"]["extrema_points"] = dict(row(r["mesh"], ref), ms=ms,
+                                                  nodes=int((r["nodes"][:, 0] >= 0).sum().item()),
+                                                  counts=r["counts"].cpu().numpy().tolist())
     return out
 
 

@@ -223,6 +223,27 @@ int64_t sdd_layout_node_count(const sdd_layout* L, int32_t k);
 sdd_status sdd_layout_nodes(sdd_ctx* ctx, const sdd_layout* L, int32_t k, int32_t placement, const sdd_density* w,
                             double* nodes, void* stream);
 
+/* Interface points at the extrema of the density's first and second
+ * derivatives along every segment (Sec. 3.6 places the Monte Carlo points
+ * at the maxima and minima of the first and second derivatives of the
+ * monitor function along the dividing lines).  Per segment (open interval):
+ * the derivative along the line from the analytic gradient of w at 4097
+ * equally spaced samples, the second derivative from its central
+ * differences; a strict local extremum of either on the samples is moved to
+ * the vertex of the parabola through its three samples; the points are
+ * sorted and a point closer than one sample to the previous one is dropped
+ * (at most 64 extrema of each derivative are examined).
+ *   nodes   device [sdd_layout_node_count(L, cap)][2]: the crosspoints,
+ *           then cap slots per segment (segment order of sdd_layout_nodes)
+ *           holding its points in increasing parameter, then (-1, -1)
+ *           (off the square: sdd_interface_estimate walks nothing there
+ *           and gives NaN)
+ *   counts  device int32 [number of segments]: points found per segment;
+ *           the first min(counts[s], cap) slots are used
+ * Pass the same cap and counts to sdd_fill_interfaces_counts. */
+sdd_status sdd_layout_nodes_extrema(sdd_ctx* ctx, const sdd_layout* L, const sdd_density* w, int32_t cap,
+                                    double* nodes, int32_t* counts, void* stream);
+
 /* One-dimensional edge data (Sec. 3.2: tangential boundary values from the
  * 1D generator): on each side the tangential coordinate is
  * int_0^s 1/w / int_0^1 1/w along that side (cumulative Simpson on the
@@ -245,6 +266,14 @@ sdd_status sdd_bmap_edge1d_table(sdd_ctx* ctx, const sdd_density* w, int32_t n_p
 sdd_status sdd_fill_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t k, const sdd_bmap* bmap,
                                const double* nodes, const double* values, int32_t interp, double* vert,
                                double* horiz, void* stream);
+
+/* As sdd_fill_interfaces for a node list of cap slots per segment of which
+ * segment s uses the first min(counts[s], cap) (device int32 counts, e.g.
+ * from sdd_layout_nodes_extrema); a segment with no points is interpolated
+ * between its ends. */
+sdd_status sdd_fill_interfaces_counts(sdd_ctx* ctx, const sdd_layout* L, int32_t cap, const int32_t* counts,
+                                      const sdd_bmap* bmap, const double* nodes, const double* values,
+                                      int32_t interp, double* vert, double* horiz, void* stream);
 
 /* ------------------------------------------------------------ subdomains ---
  * Independent Dirichlet solves of every subdomain (Sec. 2.1: solved once, no

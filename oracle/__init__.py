@@ -235,7 +235,7 @@ def bridge_exit_prob(p, q, dt: float):
 def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: float, seed: int,
                        prec: str = "fp64", t_max: float = 8.0, node_ids=None, path_begin: int = 0,
                        per_path: bool = False, proj_mode: int = 0, nthreads: int = 0,
-                       bridge: bool = False) -> dict:
+                       bridge: bool = False, allow_off: bool = False) -> dict:
     """Monte Carlo estimate of (x, y) at every node (eq. (7a), Sec. 2.2).
 
     bridge=True adds the Brownian-bridge exit test after every step (the
@@ -246,6 +246,20 @@ def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: f
     B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, density)
     D = make_density(density)
     nodes = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 2)
+    if allow_off:
+        # nodes off the open square walk nothing and get NaN; the others keep
+        # their list index as counter word g
+        inside = (nodes[:, 0] > 0) & (nodes[:, 0] < 1) & (nodes[:, 1] > 0) & (nodes[:, 1] < 1)
+        idx = np.flatnonzero(inside) if node_ids is None else np.asarray(node_ids)[inside]
+        sub = interface_estimate(density, B, nodes[inside], paths, dt, seed, prec, t_max, idx, path_begin,
+                                 per_path, proj_mode, nthreads, bridge)
+        out = dict(sub)
+        for key, width in (("mean", 2), ("se", 2), ("sums", 4)):
+            full = np.full((nodes.shape[0], width), np.nan)
+            full[inside] = sub[key]
+            out[key] = full
+        out["paths"] = int(nodes.shape[0]) * int(paths)
+        return out
     n = nodes.shape[0]
     ids = None if node_ids is None else np.ascontiguousarray(node_ids, dtype=np.int64)
     mean = np.empty((n, 2))
@@ -372,6 +386,81 @@ def layout_nodes(L: dict, k: int, placement: str = "uniform", density: Optional[
     return np.array(pts, dtype=np.float64).reshape(-1, 2)
 
 
+EXTREMA_PANELS = 4096
+
+
+def _sampled_extrema(f: np.ndarray, q0: int, q1: int, s: np.ndarray, h: float) -> list:
+    """Strict local extrema of samples f at q in [q0, q1] (the differences on
+    either side have opposite signs), each moved to the vertex of the
+    parabola through its three samples."""
+    out = []
+    for q in range(q0, q1 + 1):
+        d0, d1 = f[q] - f[q - 1], f[q + 1] - f[q]
+        if d0 * d1 < 0.0:
+            delta = 0.5 * (f[q - 1] - f[q + 1]) / (f[q - 1] - 2.0 * f[q] + f[q + 1])
+            out.append(s[q] + delta * h)
+    return out
+
+
+def extrema_params(density: dict, fixed: float, vertical: bool, a: float, b: float) -> np.ndarray:
+    """Parameters on the segment [a, b] of an interface line where the
+    density's first or second derivative along the line has a local extremum
+    (Sec. 3.6 places the Monte Carlo points at the maxima and minima of the
+    first and second derivatives of the monitor function along the dividing
+    lines).  The derivative comes from the analytic gradient at M + 1 = 4097
+    samples, the second derivative from its central differences; extrema
+    are located on the samples and refined by a parabola; points closer than
+    one sample to the previous one are dropped."""
+    M = EXTREMA_PANELS
+    h = (b - a) / M
+    s = a + (b - a) * np.arange(M + 1) / M
+    pts = np.stack([np.full(M + 1, fixed), s], 1) if vertical else np.stack([s, np.full(M + 1, fixed)], 1)
+    _, g = density_eval(density, pts)
+    f1 = g[:, 1] if vertical else g[:, 0]
+    f2 = np.zeros(M + 1)
+    f2[1:M] = (f1[2:] - f1[:-2]) / (2.0 * h)
+    cand = sorted(_sampled_extrema(f1, 1, M - 1, s, h) + _sampled_extrema(f2, 2, M - 2, s, h))
+    kept = []
+    for t in cand:
+        if not kept or t - kept[-1] >= h:
+            kept.append(t)
+    return np.array(kept, dtype=np.float64)
+
+
+def layout_nodes_extrema(L: dict, density: dict, cap: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Node list with the crosspoints first and then `cap` slots per segment
+    (segments in the order of layout_nodes): segment s holds its extrema
+    points (extrema_params, increasing) in its first min(count, cap) slots
+    and (-1, -1) in the rest.  Returns (nodes, counts) with the number of
+    points each segment found."""
+    nx, ny, sx, sy, mx, my = check_layout(L)
+    ncross = (sx - 1) * (sy - 1)
+    nseg = (sx - 1) * sy + (sy - 1) * sx
+    nodes = np.full((ncross + nseg * cap, 2), -1.0)
+    counts = np.zeros(nseg, dtype=np.int32)
+    c = 0
+    for b in range(1, sy):
+        for a in range(1, sx):
+            nodes[c] = (a / sx, b / sy)
+            c += 1
+    seg = 0
+    for a in range(1, sx):
+        for b in range(sy):
+            t = extrema_params(density, a / sx, True, b / sy, (b + 1) / sy)
+            counts[seg] = t.size
+            k = min(t.size, cap)
+            nodes[ncross + seg * cap: ncross + seg * cap + k] = np.stack([np.full(k, a / sx), t[:k]], 1)
+            seg += 1
+    for b in range(1, sy):
+        for a in range(sx):
+            t = extrema_params(density, b / sy, False, a / sx, (a + 1) / sx)
+            counts[seg] = t.size
+            k = min(t.size, cap)
+            nodes[ncross + seg * cap: ncross + seg * cap + k] = np.stack([t[:k], np.full(k, b / sy)], 1)
+            seg += 1
+    return nodes, counts
+
+
 # ------------------------------------------------------------------ fill
 
 def pchip_slopes(t: np.ndarray, v: np.ndarray) -> np.ndarray:
@@ -426,12 +515,14 @@ def interp_segment(t: np.ndarray, v: np.ndarray, te: np.ndarray, kind: str) -> n
 
 
 def fill_interfaces(L: dict, k: int, bmap, nodes: np.ndarray, values: np.ndarray, interp: str,
-                    density: Optional[dict] = None) -> Tuple[np.ndarray, np.ndarray]:
+                    density: Optional[dict] = None, counts: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
     """All interface mesh values from the node estimates (Sec. 3.6).
 
     Returns (vert[sx-1][ny][2], horiz[sy-1][nx][2]).  Line ends take the
     boundary map, crosspoints their own estimate, segment interiors the
     interpolant through (start, k nodes, end) in the segment parameter.
+    With `counts`, every segment has k slots of which it uses the first
+    min(counts[s], k).
     """
     nx, ny, sx, sy, mx, my = check_layout(L)
     B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, density)
@@ -445,6 +536,7 @@ def fill_interfaces(L: dict, k: int, bmap, nodes: np.ndarray, values: np.ndarray
     vert = np.empty((max(sx - 1, 0), ny, 2))
     horiz = np.empty((max(sy - 1, 0), nx, 2))
     base = ncross
+    segno = 0
     eta_mesh = np.arange(ny) / (ny - 1)
     xi_mesh = np.arange(nx) / (nx - 1)
     for a in range(1, sx):
@@ -457,8 +549,10 @@ def fill_interfaces(L: dict, k: int, bmap, nodes: np.ndarray, values: np.ndarray
             t0, t1 = b / sy, (b + 1) / sy
             v0 = vert[a - 1, 0] if b == 0 else cross(a, b)
             v1 = vert[a - 1, ny - 1] if b == sy - 1 else cross(a, b + 1)
-            seg = slice(base, base + k)
+            used = k if counts is None else min(int(counts[segno]), k)
+            seg = slice(base, base + used)
             base += k
+            segno += 1
             t = np.concatenate([[t0], nodes[seg, 1], [t1]])
             vv = np.concatenate([[v0], values[seg], [v1]])
             j = np.arange(b * my + 1, (b + 1) * my)
@@ -474,8 +568,10 @@ def fill_interfaces(L: dict, k: int, bmap, nodes: np.ndarray, values: np.ndarray
             t0, t1 = a / sx, (a + 1) / sx
             v0 = horiz[b - 1, 0] if a == 0 else cross(a, b)
             v1 = horiz[b - 1, nx - 1] if a == sx - 1 else cross(a + 1, b)
-            seg = slice(base, base + k)
+            used = k if counts is None else min(int(counts[segno]), k)
+            seg = slice(base, base + used)
             base += k
+            segno += 1
             t = np.concatenate([[t0], nodes[seg, 0], [t1]])
             vv = np.concatenate([[v0], values[seg], [v1]])
             i = np.arange(a * mx + 1, (a + 1) * mx)
@@ -618,10 +714,14 @@ def pipeline(cfg: dict, nthreads: int = 0) -> dict:
     dens = cfg["density"]
     B = Bmap(cfg["bmap"], dens)
     L = cfg["layout"]
-    nodes = layout_nodes(L, cfg["k"], cfg.get("placement", "uniform"), dens)
+    counts = None
+    if cfg.get("placement") == "extrema":
+        nodes, counts = layout_nodes_extrema(L, dens, cfg["k"])
+    else:
+        nodes = layout_nodes(L, cfg["k"], cfg.get("placement", "uniform"), dens)
     est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
-                             nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge")
-    vert, horiz = fill_interfaces(L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"))
+                             nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge", allow_off=True)
+    vert, horiz = fill_interfaces(L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"), counts=counts)
     if cfg.get("smooth_span", 0) > 0:
         vert, horiz = smooth_interfaces(L, vert, horiz, int(cfg["smooth_span"]))
     mesh = subdomain_solve(dens, B, L, vert, horiz)

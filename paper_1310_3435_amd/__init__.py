@@ -113,6 +113,11 @@ def lib() -> C.CDLL:
     L.sdd_subdomain_solve.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), C.POINTER(sdd_layout), P, P,
                                       D, I32, P, P, P, P, SZ, P]
     L.sdd_subdomain_solve.restype = C.c_int
+    L.sdd_layout_nodes_extrema.argtypes = [P, C.POINTER(sdd_layout), C.POINTER(sdd_density), I32, P, P, P]
+    L.sdd_layout_nodes_extrema.restype = C.c_int
+    L.sdd_fill_interfaces_counts.argtypes = [P, C.POINTER(sdd_layout), I32, P, C.POINTER(sdd_bmap), P, P, I32, P, P,
+                                             P]
+    L.sdd_fill_interfaces_counts.restype = C.c_int
     L.sdd_grid_nodes.argtypes = [P, I32, I32, P, P]
     L.sdd_grid_nodes.restype = C.c_int
     L.sdd_assemble_mesh.argtypes = [P, I32, I32, C.POINTER(sdd_bmap), P, P, P]
@@ -155,7 +160,8 @@ EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd
            "sdd_server_submit", "sdd_server_poll", "sdd_server_wait", "sdd_server_cancel", "sdd_server_clock",
            "sdd_server_destroy", "sdd_quality_workspace_bytes", "sdd_mesh_quality", "sdd_mesh_compare",
            "sdd_smooth_workspace_bytes", "sdd_mesh_smooth", "sdd_smooth_interfaces_workspace_bytes",
-           "sdd_smooth_interfaces", "sdd_grid_nodes", "sdd_assemble_mesh"]
+           "sdd_smooth_interfaces", "sdd_grid_nodes", "sdd_assemble_mesh", "sdd_layout_nodes_extrema",
+           "sdd_fill_interfaces_counts"]
 
 
 def _check(rc: int, what: str):
@@ -345,6 +351,22 @@ def sdd_layout_nodes(ctx: Context, layout: dict, k: int, placement: str = "unifo
     return nodes[:n]
 
 
+def sdd_layout_nodes_extrema(ctx: Context, layout: dict, density: dict, cap: int, stream=None):
+    """(nodes, counts): crosspoints, then `cap` slots per segment holding the
+    extrema of w_s and w_ss along it (Sec. 3.6); unused slots are (-1, -1)."""
+    torch = _torch()
+    L = make_layout(layout)
+    n = sdd_layout_node_count(layout, cap)
+    nseg = (L.sx - 1) * L.sy + (L.sy - 1) * L.sx
+    dev = f"cuda:{ctx.device}"
+    nodes = torch.empty((max(n, 1), 2), dtype=torch.float64, device=dev)
+    counts = torch.zeros(max(nseg, 1), dtype=torch.int32, device=dev)
+    D = make_density(density)
+    _check(lib().sdd_layout_nodes_extrema(ctx.h, C.byref(L), C.byref(D), int(cap), _ptr(nodes), _ptr(counts),
+                                          _stream(stream)), "sdd_layout_nodes_extrema")
+    return nodes[:n], counts[:nseg]
+
+
 def sdd_bmap_edge1d_table(ctx: Context, density: dict, n_per_edge: int = 4097, stream=None):
     torch = _torch()
     D = make_density(density)
@@ -355,16 +377,23 @@ def sdd_bmap_edge1d_table(ctx: Context, density: dict, n_per_edge: int = 4097, s
 
 
 def sdd_fill_interfaces(ctx: Context, layout: dict, k: int, bmap, nodes, values, interp: str = "linear",
-                        stream=None, density: Optional[dict] = None) -> Tuple[object, object]:
+                        stream=None, density: Optional[dict] = None, counts=None) -> Tuple[object, object]:
+    """Interface lines from the node estimates; with `counts` (device int32)
+    the node list has k slots per segment (sdd_fill_interfaces_counts)."""
     torch = _torch()
     B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, ctx, density)
     L = make_layout(layout)
     f64 = dict(dtype=torch.float64, device=f"cuda:{ctx.device}")
     vert = torch.empty((max(L.sx - 1, 0), L.ny, 2), **f64)
     horiz = torch.empty((max(L.sy - 1, 0), L.nx, 2), **f64)
-    rc = lib().sdd_fill_interfaces(ctx.h, C.byref(L), int(k), C.byref(B.s), _ptr(nodes), _ptr(values),
-                                   INTERP[interp], _ptr(vert) if vert.numel() else None,
-                                   _ptr(horiz) if horiz.numel() else None, _stream(stream))
+    pv = _ptr(vert) if vert.numel() else None
+    ph = _ptr(horiz) if horiz.numel() else None
+    if counts is None:
+        rc = lib().sdd_fill_interfaces(ctx.h, C.byref(L), int(k), C.byref(B.s), _ptr(nodes), _ptr(values),
+                                       INTERP[interp], pv, ph, _stream(stream))
+    else:
+        rc = lib().sdd_fill_interfaces_counts(ctx.h, C.byref(L), int(k), _ptr(counts), C.byref(B.s), _ptr(nodes),
+                                              _ptr(values), INTERP[interp], pv, ph, _stream(stream))
     _check(rc, "sdd_fill_interfaces")
     return vert, horiz
 
@@ -494,11 +523,15 @@ def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -
     dens = cfg["density"]
     B = Bmap(cfg["bmap"], ctx, dens)
     L = cfg["layout"]
-    nodes = sdd_layout_nodes(ctx, L, cfg["k"], cfg.get("placement", "uniform"), dens, stream=stream)
+    counts = None
+    if cfg.get("placement") == "extrema":
+        nodes, counts = sdd_layout_nodes_extrema(ctx, L, dens, cfg["k"], stream=stream)
+    else:
+        nodes = sdd_layout_nodes(ctx, L, cfg["k"], cfg.get("placement", "uniform"), dens, stream=stream)
     est = sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
                                  per_path=per_path, stream=stream, exit_test=cfg.get("exit_test", "step"))
     vert, horiz = sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"),
-                                      stream=stream)
+                                      stream=stream, counts=counts)
     if cfg.get("smooth_span", 0) > 0:
         sdd_smooth_interfaces(ctx, L, vert, horiz, int(cfg["smooth_span"]), stream=stream)
     sol = sdd_subdomain_solve(ctx, dens, B, L, vert, horiz, stream=stream)
@@ -506,7 +539,8 @@ def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -
     if pm:
         sdd_mesh_smooth(ctx, L, sol["mesh"], pm["dt"], pm["k"], pm["steps"], pm.get("per_subdomain", True),
                         stream=stream)
-    return {"nodes": nodes, "est": est, "vert": vert, "horiz": horiz, "mesh": sol["mesh"], "sweeps": sol["sweeps"],
+    return {"nodes": nodes, "counts": counts, "est": est, "vert": vert, "horiz": horiz, "mesh": sol["mesh"],
+            "sweeps": sol["sweeps"],
             "resid": sol["resid"], "_keep": (B, sol)}
 
 

@@ -169,7 +169,37 @@ sdd_status sdd_fill_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t k, con
     if (L->sy > 1 && !horiz) return SDD_EINVAL;
     if (sdd_layout_node_count(L, k) > 0 && (!nodes || !values)) return SDD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
-    return from_hip(launch_fill(*L, k, to_device(bmap), nodes, values, interp, vert, horiz, (hipStream_t)stream));
+    return from_hip(
+        launch_fill(*L, k, nullptr, to_device(bmap), nodes, values, interp, vert, horiz, (hipStream_t)stream));
+}
+
+sdd_status sdd_layout_nodes_extrema(sdd_ctx* ctx, const sdd_layout* L, const sdd_density* w, int32_t cap,
+                                    double* nodes, int32_t* counts, void* stream)
+{
+    if (!ctx || !nodes || !counts || cap < 0) return SDD_EINVAL;
+    sdd_status s = check_layout(L);
+    if (s != SDD_OK) return s;
+    if ((s = check_density(w)) != SDD_OK) return s;
+    if (sdd_layout_node_count(L, cap) == 0) return SDD_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(launch_layout_extrema(*L, cap, to_device(w), nodes, counts, (hipStream_t)stream));
+}
+
+sdd_status sdd_fill_interfaces_counts(sdd_ctx* ctx, const sdd_layout* L, int32_t cap, const int32_t* counts,
+                                      const sdd_bmap* bmap, const double* nodes, const double* values,
+                                      int32_t interp, double* vert, double* horiz, void* stream)
+{
+    if (!ctx || !counts) return SDD_EINVAL;
+    sdd_status s = check_layout(L);
+    if (s != SDD_OK) return s;
+    if ((s = check_bmap(bmap)) != SDD_OK) return s;
+    if (cap < 0 || interp < 0 || interp > 1) return SDD_EINVAL;
+    if (L->sx > 1 && !vert) return SDD_EINVAL;
+    if (L->sy > 1 && !horiz) return SDD_EINVAL;
+    if (sdd_layout_node_count(L, cap) > 0 && (!nodes || !values)) return SDD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return from_hip(
+        launch_fill(*L, cap, counts, to_device(bmap), nodes, values, interp, vert, horiz, (hipStream_t)stream));
 }
 
 size_t sdd_subdomain_workspace_bytes(const sdd_layout* L)

@@ -52,8 +52,10 @@ hipError_t launch_walk(const WalkArgs& A, int prec, double* mean, double* se, do
 hipError_t launch_layout_nodes(const sdd_layout& L, int k, int placement, const Density& D, double* nodes,
                                hipStream_t stream);
 hipError_t launch_edge1d_table(const Density& D, int n, double* table, hipStream_t stream);
-hipError_t launch_fill(const sdd_layout& L, int k, const Bmap& B, const double* nodes, const double* values,
-                       int interp, double* vert, double* horiz, hipStream_t stream);
+hipError_t launch_layout_extrema(const sdd_layout& L, int cap, const Density& D, double* nodes, int32_t* counts,
+                                 hipStream_t stream);
+hipError_t launch_fill(const sdd_layout& L, int k, const int32_t* counts, const Bmap& B, const double* nodes,
+                       const double* values, int interp, double* vert, double* horiz, hipStream_t stream);
 hipError_t launch_subdomain_solve(const Density& D, const Bmap& B, const sdd_layout& L, const double* vert,
                                   const double* horiz, double tol, int max_sweeps, double* mesh, int32_t* sweeps,
                                   double* resid, void* workspace, hipStream_t stream);

@@ -136,6 +136,126 @@ hipError_t launch_layout_nodes(const sdd_layout& L, int k, int placement, const 
     return hipGetLastError();
 }
 
+// Placement at the extrema of the density's first and second derivatives
+// along each segment (Sec. 3.6).  One block per segment: the derivative
+// along the line from the analytic gradient at 4097 samples and the second
+// derivative from its central differences, both in LDS; strict local
+// extrema of either on the samples, moved to the vertex of the parabola
+// through their three samples; sorted; a point closer than one sample to
+// the previous kept one is dropped.  counts[s] = points kept; the segment's
+// cap slots hold them in increasing order, then (-1, -1).  At most
+// kExtremaMax extrema of each derivative are examined per segment.
+constexpr int kExtremaPanels = 4096;
+constexpr int kExtremaMax = 64;
+
+__device__ __forceinline__ double parabola_vertex(const double* f, int q, double sq, double h)
+{
+    const double delta = 0.5 * (f[q - 1] - f[q + 1]) / (f[q - 1] - 2.0 * f[q] + f[q + 1]);
+    return sq + delta * h;
+}
+
+__global__ __launch_bounds__(256) void layout_extrema_kernel(sdd_layout L, int cap, const Density D,
+                                                             double* __restrict__ nodes, int32_t* __restrict__ counts)
+{
+    __shared__ double f1[kExtremaPanels + 1];
+    __shared__ double f2[kExtremaPanels + 1];
+    __shared__ double cand[2 * kExtremaMax];
+    __shared__ int ncand[2];
+    __shared__ int kept;
+    const int sx = L.sx, sy = L.sy;
+    const int ncross = (sx - 1) * (sy - 1);
+    if (blockIdx.x == 0) {
+        for (int c = threadIdx.x; c < ncross; c += blockDim.x) {
+            const int a = 1 + c % (sx - 1), b = 1 + c / (sx - 1);
+            nodes[2 * c] = (double)a / sx;
+            nodes[2 * c + 1] = (double)b / sy;
+        }
+        return;
+    }
+    const int seg = blockIdx.x - 1;
+    const int nvert = (sx - 1) * sy;
+    bool vertical;
+    double fixed, a0, a1;
+    if (seg < nvert) {
+        vertical = true;
+        const int a = 1 + seg / sy, b = seg % sy;
+        fixed = (double)a / sx;
+        a0 = (double)b / sy;
+        a1 = (double)(b + 1) / sy;
+    } else {
+        vertical = false;
+        const int hs = seg - nvert;
+        const int b = 1 + hs / sx, a = hs % sx;
+        fixed = (double)b / sy;
+        a0 = (double)a / sx;
+        a1 = (double)(a + 1) / sx;
+    }
+    const int M = kExtremaPanels;
+    const double h = (a1 - a0) / M;
+    auto sample = [&](int q) { return a0 + ((a1 - a0) * q) / M; };
+    if (threadIdx.x < 2) ncand[threadIdx.x] = 0;
+    for (int q = threadIdx.x; q <= M; q += blockDim.x) {
+        const double sq = sample(q);
+        double w, gx, gy;
+        density_grad(D, vertical ? fixed : sq, vertical ? sq : fixed, w, gx, gy);
+        f1[q] = vertical ? gy : gx;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q <= M; q += blockDim.x)
+        f2[q] = (q >= 1 && q <= M - 1) ? (f1[q + 1] - f1[q - 1]) / (2.0 * h) : 0.0;
+    __syncthreads();
+    for (int q = threadIdx.x; q <= M; q += blockDim.x) {
+        if (q >= 1 && q <= M - 1 && (f1[q] - f1[q - 1]) * (f1[q + 1] - f1[q]) < 0.0) {
+            const int slot = atomicAdd(&ncand[0], 1);
+            if (slot < kExtremaMax) cand[slot] = parabola_vertex(f1, q, sample(q), h);
+        }
+        if (q >= 2 && q <= M - 2 && (f2[q] - f2[q - 1]) * (f2[q + 1] - f2[q]) < 0.0) {
+            const int slot = atomicAdd(&ncand[1], 1);
+            if (slot < kExtremaMax) cand[kExtremaMax + slot] = parabola_vertex(f2, q, sample(q), h);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int n1 = min(ncand[0], kExtremaMax), n2 = min(ncand[1], kExtremaMax);
+        // gather both lists at the front, insertion sort, drop near duplicates
+        for (int i = 0; i < n2; ++i) cand[n1 + i] = cand[kExtremaMax + i];
+        const int n = n1 + n2;
+        for (int i = 1; i < n; ++i) {
+            const double v = cand[i];
+            int j = i - 1;
+            while (j >= 0 && cand[j] > v) {
+                cand[j + 1] = cand[j];
+                --j;
+            }
+            cand[j + 1] = v;
+        }
+        int m = 0;
+        for (int i = 0; i < n; ++i)
+            if (m == 0 || cand[i] - cand[m - 1] >= h) cand[m++] = cand[i];
+        kept = m;
+        counts[seg] = m;
+    }
+    __syncthreads();
+    double* out = nodes + 2 * ((int64_t)ncross + (int64_t)seg * cap);
+    for (int i = threadIdx.x; i < cap; i += blockDim.x) {
+        if (i < kept) {
+            out[2 * i] = vertical ? fixed : cand[i];
+            out[2 * i + 1] = vertical ? cand[i] : fixed;
+        } else {
+            out[2 * i] = -1.0;
+            out[2 * i + 1] = -1.0;
+        }
+    }
+}
+
+hipError_t launch_layout_extrema(const sdd_layout& L, int cap, const Density& D, double* nodes, int32_t* counts,
+                                 hipStream_t stream)
+{
+    const int nseg = (L.sx - 1) * L.sy + (L.sy - 1) * L.sx;
+    hipLaunchKernelGGL(layout_extrema_kernel, dim3(1 + nseg), dim3(256), 0, stream, L, cap, D, nodes, counts);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ edge data
 
 // One block per side; table[side][q] = (normal, tangential) per the side.
@@ -268,7 +388,8 @@ __device__ void interp_at(const Segment& S, double t, int interp, double out[2])
 }
 
 // One thread per point of every interface line.
-__global__ __launch_bounds__(256) void fill_kernel(sdd_layout L, int k, const Bmap B, const double* __restrict__ nodes,
+__global__ __launch_bounds__(256) void fill_kernel(sdd_layout L, int k, const int32_t* __restrict__ counts,
+                                                   const Bmap B, const double* __restrict__ nodes,
                                                    const double* __restrict__ values, int interp,
                                                    double* __restrict__ vert, double* __restrict__ horiz)
 {
@@ -343,6 +464,7 @@ __global__ __launch_bounds__(256) void fill_kernel(sdd_layout L, int k, const Bm
                                    : (int64_t)(sx - 1) * sy + (int64_t)(line - 1) * sx + seg;
     S.nodes = nodes + 2 * (ncross + first * k);
     S.values = values + 2 * (ncross + first * k);
+    if (counts) S.k = min(counts[first], k);  // k slots per segment, the first counts[] used
     const double t = (double)j / (n_along - 1);
     double v[2];
     interp_at(S, t, interp, v);
@@ -350,13 +472,13 @@ __global__ __launch_bounds__(256) void fill_kernel(sdd_layout L, int k, const Bm
     out[1] = v[1];
 }
 
-hipError_t launch_fill(const sdd_layout& L, int k, const Bmap& B, const double* nodes, const double* values,
-                       int interp, double* vert, double* horiz, hipStream_t stream)
+hipError_t launch_fill(const sdd_layout& L, int k, const int32_t* counts, const Bmap& B, const double* nodes,
+                       const double* values, int interp, double* vert, double* horiz, hipStream_t stream)
 {
     const int64_t total = (int64_t)(L.sx - 1) * L.ny + (int64_t)(L.sy - 1) * L.nx;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, L, k, B, nodes,
-                       values, interp, vert, horiz);
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, L, k, counts, B,
+                       nodes, values, interp, vert, horiz);
     return hipGetLastError();
 }
 

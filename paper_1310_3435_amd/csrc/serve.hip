@@ -693,7 +693,7 @@ void finish(sdd_server* S, Request* r)
         e = hipGetLastError();
     }
     const Bmap B = to_device(&q.bmap);
-    if (e == hipSuccess) e = launch_fill(q.layout, q.k, B, r->nodes, r->mean, q.interp, r->vert, r->horiz, st);
+    if (e == hipSuccess) e = launch_fill(q.layout, q.k, nullptr, B, r->nodes, r->mean, q.interp, r->vert, r->horiz, st);
     if (e == hipSuccess)
         e = launch_subdomain_solve(to_device(&q.w), B, q.layout, r->vert, r->horiz, 1e-13, 100000, r->mesh, nullptr,
                                    nullptr, r->fd_ws, st);

@@ -158,3 +158,37 @@ def test_pipeline_annulus_small_matches_oracle(ctx, ref):
     err = np.max(np.abs(out["mesh"].cpu().numpy() - r["mesh"]))
     say(f"pipeline annulus max |GPU - oracle| = {err:.3e}")
     assert err <= 1e-9
+
+
+@pytest.mark.parametrize("cap", [2, 8])
+@pytest.mark.parametrize("dseed,layout", [(3, {"nx": 33, "ny": 33, "sx": 2, "sy": 2}),
+                                          (8, {"nx": 49, "ny": 37, "sx": 4, "sy": 3})])
+def test_extrema_placement_matches_oracle(ctx, ref, cap, dseed, layout):
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    d = W.random_density(dseed, 4)
+    say(f"extrema placement seed {dseed} layout {layout} cap {cap}")
+    nodes, counts = sdd.sdd_layout_nodes_extrema(ctx, layout, d, cap)
+    g, gc = nodes.cpu().numpy(), counts.cpu().numpy()
+    torch.cuda.synchronize()
+    r, rc = ref.layout_nodes_extrema(layout, d, cap)
+    say(f"counts {gc.tolist()}")
+    assert np.array_equal(gc, rc) and gc.sum() > 0
+    assert np.abs(g - r).max() <= 1e-9
+
+
+def test_extrema_pipeline_matches_oracle(ctx, ref):
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    c = dict(W.cfg_paper_example(), placement="extrema", k=8, paths=1000, prec="fp64", exit_test="step")
+    say("pipeline with extrema placement")
+    g = sdd.run_pipeline(ctx, c)
+    mesh, counts = g["mesh"].cpu().numpy(), g["counts"].cpu().numpy()
+    torch.cuda.synchronize()
+    r = ref.pipeline(c)
+    d = np.abs(mesh - r["mesh"]).max()
+    say(f"extrema pipeline: counts {counts.tolist()}, max diff {d:.3e}")
+    assert counts.sum() > 0 and np.all(np.isfinite(mesh))
+    assert d <= 1e-9

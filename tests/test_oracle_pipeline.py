@@ -237,3 +237,53 @@ def test_whole_grid_mesh_of_constant_density_is_the_identity(ref):
     assert np.all(err <= 4 * r["est"]["se"] + 4e-4)
     m = r["mesh"]
     assert np.allclose(m[0, :, 0], np.arange(9) / 8) and np.allclose(m[:, 0, 1], np.arange(7) / 6)
+
+
+def test_extrema_of_a_gaussian_crossing_the_line(ref):
+    # w = 1 + A exp(-c((xi - 0.3)^2 + (eta - 0.55)^2)) along the vertical line
+    # xi = 0.3: f = exp(-c u^2), u = eta - 0.55; f' has extrema at
+    # u^2 = 1/(2c), f'' at u = 0 and u^2 = 3/(2c)
+    c = 60.0
+    d = {"base": 1.0, "terms": [{"kind": "gauss", "amp": 5.0, "coef": c, "cx": 0.3, "cy": 0.55}]}
+    t = ref.extrema_params(d, 0.3, True, 0.0, 1.0)
+    u1, u2 = 1 / math.sqrt(2 * c), math.sqrt(3 / (2 * c))
+    want = np.sort(0.55 + np.array([-u2, -u1, 0.0, u1, u2]))
+    assert t.shape == (5,)
+    assert np.abs(t - want).max() < 1e-6
+    # the same bump along a horizontal line through its centre
+    t = ref.extrema_params(d, 0.55, False, 0.0, 1.0)
+    assert np.abs(t - np.sort(0.3 + np.array([-u2, -u1, 0.0, u1, u2]))).max() < 1e-6
+    # restricted to a segment, only the extrema inside it
+    t = ref.extrema_params(d, 0.3, True, 0.5, 1.0)
+    assert np.abs(t - want[want > 0.5]).max() < 1e-6
+
+
+def test_extrema_of_sin2_and_of_a_constant(ref):
+    # w = 1 + 3 sin^2(2 pi xi): w_xi = 6 pi sin(4 pi xi) has extrema at 1/8, 3/8;
+    # w_xixi = 24 pi^2 cos(4 pi xi) at 1/4 (0 and 1/2 are the segment ends)
+    d = {"base": 1.0, "terms": [{"kind": "sin2", "amp": 3.0, "coef": 2 * math.pi, "nx": 1.0, "ny": 0.0}]}
+    t = ref.extrema_params(d, 0.5, False, 0.0, 0.5)
+    assert np.abs(t - np.array([0.125, 0.25, 0.375])).max() < 1e-7
+    flat = {"base": 2.0, "terms": []}
+    assert ref.extrema_params(flat, 0.5, True, 0.0, 1.0).size == 0
+
+
+def test_extrema_layout_and_fill_with_counts(ref):
+    d = {"base": 1.0, "terms": [{"kind": "gauss", "amp": 5.0, "coef": 60.0, "cx": 0.3, "cy": 0.55}]}
+    L = {"nx": 33, "ny": 33, "sx": 2, "sy": 2}
+    nodes, counts = ref.layout_nodes_extrema(L, d, 4)
+    assert nodes.shape == (1 + 4 * 4, 2) and counts.shape == (4,)
+    # the vertical line xi = 1/2 is 0.2 from the bump centre: its extrema
+    # split between the two segments; unused slots are off the square
+    for s in range(4):
+        k = min(counts[s], 4)
+        slot = nodes[1 + 4 * s: 1 + 4 * s + 4]
+        assert np.all(slot[k:] == -1.0) and np.all((slot[:k] > 0) & (slot[:k] < 1))
+    # linear data along the lines are reproduced by the fill whatever the counts
+    vals = np.where(nodes >= 0, 0.3 + 0.2 * nodes, np.nan)
+    vert, horiz = ref.fill_interfaces(L, 4, {"kind": "affine", "p": [0.3, 0.2, 0.0, 0.0, 0.0, 0.2]}, nodes,
+                                      vals * np.array([1.0, 1.0]) + np.array([0.0, -0.3]), "pchip",
+                                      counts=counts)
+    eta = np.arange(33) / 32
+    assert np.allclose(vert[0, :, 0], 0.3 + 0.2 * 0.5) and np.allclose(vert[0, :, 1], 0.2 * eta)
+    assert np.all(np.isfinite(horiz))
