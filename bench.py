@@ -51,7 +51,7 @@ FP32_PEAK_TFLOPS = 157.3
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("walk.hip", "common.h", "kernels.h", "rng.h"):
+    for f in ("walk.hip", "walk.h", "common.h", "rng.h"):
         with open(os.path.join(ROOT, "paper_1310_3435_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

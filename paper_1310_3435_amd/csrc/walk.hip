@@ -19,8 +19,8 @@
 #include <stdlib.h>
 
 #include "common.h"
-#include "kernels.h"
 #include "rng.h"
+#include "walk.h"
 
 namespace sdd {
 
