@@ -76,9 +76,22 @@ def traffic_from_profile(workload: str):
         return None
 
 
-def cpu_baseline(cfg, nodes, sample_nodes: int):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int):
     """The oracle, untuned, on this host's cores: `sample_nodes` evenly spaced
-    nodes of the same workload at its full paths per node, double precision."""
+    nodes of the same workload at its full paths per node, double precision;
+    then one node on one core.  The full workload's oracle time is
+    extrapolated linearly in steps from the all-core rate."""
     import numpy as np
 
     import oracle
@@ -94,10 +107,19 @@ def cpu_baseline(cfg, nodes, sample_nodes: int):
     r = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[idx], cfg["paths"], cfg["dt"], cfg["seed"],
                                   "fp64", node_ids=idx, nthreads=threads)
     el = time.perf_counter() - t0
-    return {"value": r["steps"] / el, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
+    one = idx[sample_nodes // 2: sample_nodes // 2 + 1]
+    t0 = time.perf_counter()
+    r1 = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[one], cfg["paths"], cfg["dt"], cfg["seed"],
+                                   "fp64", node_ids=one, nthreads=1)
+    el1 = time.perf_counter() - t0
+    rate = r["steps"] / el
+    return {"value": rate, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{sample_nodes} of {n} nodes (indices i*{n // sample_nodes}), {cfg['paths']} paths/node, "
                       f"dt={cfg['dt']}, fp64 walk, {r['steps']} steps in {el:.2f} s",
-            "nodes_per_s": sample_nodes / el}
+            "nodes_per_s": sample_nodes / el, "cpu": cpu_model(),
+            "single_core": {"value": r1["steps"] / el1, "unit": "walk steps/s",
+                            "sample": f"node {int(one[0])}, {cfg['paths']} paths, {r1['steps']} steps in {el1:.2f} s"},
+            "full_workload_s_extrapolated": full_steps / rate}
 
 
 def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, bridge_dt: float = 0.0):
@@ -521,6 +543,7 @@ def main():
             "cycles_per_wave_step": per_step,
             "fp32_tflops": tflops,
             "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,
+            "fp32_frac_of_78_6_unpacked": tflops / (FP32_PEAK_TFLOPS / 2) if tflops else None,
         },
     }
     if not args.no_fp64 and cfg["prec"] == "fp32":
@@ -550,7 +573,7 @@ def main():
         line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst,
                                      bridge_dt=args.serve_bridge_dt)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes)
+        line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes, steps_per_pass)
     print(json.dumps(line), flush=True)
 
 
