@@ -330,6 +330,14 @@ def quality_study(ctx, cfg, B, nodes, est_mean, dd_mesh):
         sdd.sdd_mesh_smooth(ctx, single, b, dt, 1000.0, m, per_subdomain=False)
         sm[str(m)] = dict(row(a, b), smooth_ms=ms)
     out["perona_malik_per_subdomain"] = {"dt": dt, "k": 1000.0, "steps": sm}
+    # a second cycle on the subdomains shifted by half their size (Sec. 4),
+    # and the whole grid, each for 10 steps after 10 per-subdomain steps
+    for name, mode in (("then_shifted_subdomains", "shifted"), ("then_whole_grid", False)):
+        a, b = dd_mesh.clone(), ref.clone()
+        sdd.sdd_mesh_smooth(ctx, L, a, dt, 1000.0, 10, per_subdomain=True)
+        _, ms = timed(lambda: sdd.sdd_mesh_smooth(ctx, L, a, dt, 1000.0, 10, per_subdomain=mode))
+        sdd.sdd_mesh_smooth(ctx, single, b, dt, 1000.0, 20, per_subdomain=False)
+        out["perona_malik_per_subdomain"][name] = dict(row(a, b), smooth_ms=ms)
     vert, horiz = sdd.sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est_mean, cfg.get("interp", "linear"))
     _, ls_ms = timed(lambda: sdd.sdd_smooth_interfaces(ctx, L, vert, horiz, 9))
     sol = sdd.sdd_subdomain_solve(ctx, dens, B, L, vert, horiz)

@@ -345,7 +345,10 @@ sdd_status sdd_mesh_compare(sdd_ctx* ctx, int32_t nx, int32_t ny, const sdd_dens
  * c_E = exp(-((u_E - u_P) / h_xi)^2 / k^2) (Perona and Malik's
  * discretisation).  The boundary ring is fixed; with per_subdomain = 1 the
  * interface lines of L are fixed too, so every subdomain is smoothed on
- * its own (Sec. 3.5); per_subdomain = 0 smooths the whole grid.
+ * its own (Sec. 3.5); per_subdomain = 2 fixes instead the lines half a
+ * subdomain (rounded down) further on, the subdomains of a second cycle
+ * whose interiors hold the original interfaces (Sec. 4); per_subdomain = 0
+ * smooths the whole grid.
  * Requires dt (2/h_xi^2 + 2/h_eta^2) <= 1 (then each step is a convex
  * combination: no new extrema), else SDD_EINVAL.  k > 0, steps >= 0.
  *   mesh       device [ny][nx][2], smoothed in place

@@ -90,26 +90,31 @@ def mesh_compare(mesh: np.ndarray, ref: np.ndarray, density: dict) -> dict:
 
 # ------------------------------------------------------------ Perona-Malik
 
-def fixed_nodes(nx: int, ny: int, L: dict = None) -> np.ndarray:
+def fixed_nodes(nx: int, ny: int, L: dict = None, shifted: bool = False) -> np.ndarray:
     """Nodes held fixed: the boundary ring and, when a layout is given, its
-    interface lines."""
+    interface lines; shifted: the lines half a subdomain further on (the
+    subdomains of a second cycle, whose interiors hold the original
+    interfaces, Sec. 4)."""
     f = np.zeros((ny, nx), dtype=bool)
     f[0, :] = f[-1, :] = f[:, 0] = f[:, -1] = True
     if L is not None:
         mx, my = (nx - 1) // L["sx"], (ny - 1) // L["sy"]
-        f[:, ::mx] = True
-        f[::my, :] = True
+        ox, oy = (mx // 2, my // 2) if shifted else (0, 0)
+        f[:, ox::mx] = True
+        f[oy::my, :] = True
     return f
 
 
-def perona_malik(mesh: np.ndarray, dt: float, k: float, steps: int, L: dict = None) -> np.ndarray:
+def perona_malik(mesh: np.ndarray, dt: float, k: float, steps: int, L: dict = None,
+                 shifted: bool = False) -> np.ndarray:
     """`steps` FTCS steps of u_t = div(exp(-|grad u|^2/k^2) grad u) for u = x
     and u = y over the computational grid (eq. (12)); L given: its interface
-    lines are fixed too, i.e. every subdomain is smoothed on its own."""
+    lines are fixed too, i.e. every subdomain is smoothed on its own (with
+    shifted, the subdomains moved by half their size)."""
     u = np.array(mesh, dtype=np.float64)
     ny, nx = u.shape[0], u.shape[1]
     hx, hy = 1.0 / (nx - 1), 1.0 / (ny - 1)
-    free = ~fixed_nodes(nx, ny, L)
+    free = ~fixed_nodes(nx, ny, L, shifted)
     for _ in range(steps):
         P = u[1:-1, 1:-1]
         dE = u[1:-1, 2:] - P

@@ -491,13 +491,16 @@ def sdd_mesh_compare(ctx: Context, density: dict, mesh, ref, stream=None):
     return out
 
 
-def sdd_mesh_smooth(ctx: Context, layout: dict, mesh, dt: float, k: float, steps: int, per_subdomain: bool = True,
+def sdd_mesh_smooth(ctx: Context, layout: dict, mesh, dt: float, k: float, steps: int, per_subdomain=True,
                     stream=None):
-    """Perona-Malik FTCS smoothing of the device mesh [ny, nx, 2] in place (eq. (12))."""
+    """Perona-Malik FTCS smoothing of the device mesh [ny, nx, 2] in place (eq. (12)).
+    per_subdomain: True (each subdomain alone), False (the whole grid) or
+    "shifted" (subdomains moved by half their size, a second cycle)."""
     torch = _torch()
     L = make_layout(layout)
+    mode = 2 if per_subdomain == "shifted" else (1 if per_subdomain else 0)
     ws = torch.empty(int(lib().sdd_smooth_workspace_bytes(C.byref(L))), dtype=torch.uint8, device=mesh.device)
-    _check(lib().sdd_mesh_smooth(ctx.h, C.byref(L), 1 if per_subdomain else 0, float(dt), float(k), int(steps),
+    _check(lib().sdd_mesh_smooth(ctx.h, C.byref(L), mode, float(dt), float(k), int(steps),
                                  _ptr(mesh), _ptr(ws), ws.numel(), _stream(stream)), "sdd_mesh_smooth")
     return mesh
 

@@ -291,7 +291,7 @@ sdd_status sdd_mesh_smooth(sdd_ctx* ctx, const sdd_layout* L, int32_t per_subdom
     if (!ctx || !mesh || !workspace) return SDD_EINVAL;
     sdd_status s = check_layout(L);
     if (s != SDD_OK) return s;
-    if (per_subdomain != 0 && per_subdomain != 1) return SDD_EINVAL;
+    if (per_subdomain < 0 || per_subdomain > 2) return SDD_EINVAL;
     if (!(dt > 0.0) || !(k > 0.0) || !is_finite(k) || steps < 0) return SDD_EINVAL;
     const double hx2 = (double)(L->nx - 1) * (L->nx - 1), hy2 = (double)(L->ny - 1) * (L->ny - 1);
     if (!(dt * (2.0 * hx2 + 2.0 * hy2) <= 1.0)) return SDD_EINVAL;  // FTCS stability

@@ -178,11 +178,12 @@ hipError_t launch_compare(int nx, int ny, const Density& D, const double* mesh, 
 // One FTCS step, src -> dst, of u_t = div(exp(-|grad u|^2/k^2) grad u) for
 // each mesh component; the face coefficient comes from the one-sided
 // difference across the face.  Fixed: the boundary ring and, when
-// mx > 0, every mx-th column and my-th row (the interface lines).
+// mx > 0, the columns i = ox (mod mx) and rows j = oy (mod my) (the
+// interface lines, or those of the subdomains shifted by ox, oy).
 __global__ __launch_bounds__(kPostBlock) void smooth_step_kernel(const double2* __restrict__ src,
                                                                  double2* __restrict__ dst, int nx, int ny, int mx,
-                                                                 int my, double dt_hx2, double dt_hy2, double ihx,
-                                                                 double ihy, double ik2)
+                                                                 int my, int ox, int oy, double dt_hx2,
+                                                                 double dt_hy2, double ihx, double ihy, double ik2)
 {
     const int i = blockIdx.x * 16 + (threadIdx.x & 15);
     const int j = blockIdx.y * 16 + (threadIdx.x >> 4);
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(kPostBlock) void smooth_step_kernel(const double2* 
     const size_t p = (size_t)j * nx + i;
     const double2 P = src[p];
     bool fixed = i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
-    if (mx > 0) fixed = fixed || (i % mx) == 0 || (j % my) == 0;
+    if (mx > 0) fixed = fixed || (i % mx) == ox || (j % my) == oy;
     if (fixed) {
         dst[p] = P;
         return;
@@ -220,12 +221,13 @@ hipError_t launch_smooth(const sdd_layout& L, int per_subdomain, double dt, doub
     const int nx = L.nx, ny = L.ny;
     const int mx = per_subdomain ? (nx - 1) / L.sx : 0;
     const int my = per_subdomain ? (ny - 1) / L.sy : 0;
+    const int ox = per_subdomain == 2 ? mx / 2 : 0, oy = per_subdomain == 2 ? my / 2 : 0;
     const double ihx = (double)(nx - 1), ihy = (double)(ny - 1);
     const dim3 grid((unsigned)((nx + 15) / 16), (unsigned)((ny + 15) / 16));
     double2* a = (double2*)mesh;
     double2* b = (double2*)ws;
     for (int s = 0; s < steps; ++s) {
-        hipLaunchKernelGGL(smooth_step_kernel, grid, dim3(kPostBlock), 0, stream, a, b, nx, ny, mx, my,
+        hipLaunchKernelGGL(smooth_step_kernel, grid, dim3(kPostBlock), 0, stream, a, b, nx, ny, mx, my, ox, oy,
                            dt * ihx * ihx, dt * ihy * ihy, ihx, ihy, 1.0 / (k * k));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

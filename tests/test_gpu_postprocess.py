@@ -84,7 +84,7 @@ def test_compare_matches_oracle(ctx, ref):
     assert g[0] == pytest.approx(r["linf"], rel=1e-13) and g[1] == pytest.approx(r["max_disp"], rel=1e-13)
 
 
-@pytest.mark.parametrize("per_subdomain", [True, False])
+@pytest.mark.parametrize("per_subdomain", [True, False, "shifted"])
 @pytest.mark.parametrize("steps", [0, 1, 4, 7])
 def test_perona_malik_matches_oracle(ctx, ref, per_subdomain, steps):
     import torch
@@ -97,7 +97,7 @@ def test_perona_malik_matches_oracle(ctx, ref, per_subdomain, steps):
     sdd.sdd_mesh_smooth(ctx, L, t, dt, 2.0, steps, per_subdomain)
     g = t.cpu().numpy()
     torch.cuda.synchronize()
-    r = ref.perona_malik(m, dt, 2.0, steps, L if per_subdomain else None)
+    r = ref.perona_malik(m, dt, 2.0, steps, L if per_subdomain else None, shifted=per_subdomain == "shifted")
     say(f"perona-malik steps={steps} per_subdomain={per_subdomain}: max diff {np.abs(g - r).max():.3e}")
     assert np.abs(g - r).max() <= 1e-13
     if steps:

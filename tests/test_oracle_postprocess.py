@@ -279,3 +279,22 @@ def test_local_regression_fixed_points_symmetry_and_noise(ref):
     fwd = ref.loess_line(vert[1], sv, fixed, 9)
     bwd = ref.loess_line(vert[1][::-1], sv, fixed[::-1], 9)[::-1]
     assert np.allclose(fwd, bwd, rtol=0, atol=1e-13)
+
+
+def test_shifted_cycle_moves_the_original_interfaces(ref):
+    # the shifted cycle fixes the lines half a subdomain away, so the original
+    # interface lines are smoothed; a cut-out shifted subdomain smoothed alone
+    # (dt x 16, k / 4 as above) equals its part of the result
+    rng = np.random.default_rng(8)
+    L = {"nx": 33, "ny": 33, "sx": 4, "sy": 4}
+    m = grid(33, 33)
+    m[1:-1, 1:-1] += rng.normal(0, 0.01, size=m[1:-1, 1:-1].shape)
+    dt, k, steps = 1e-4 / 16, 5.0, 4
+    out = ref.perona_malik(m, dt, k, steps, L, shifted=True)
+    f = ref.fixed_nodes(33, 33, L, shifted=True)
+    assert np.array_equal(out[f], m[f])
+    orig = ref.fixed_nodes(33, 33, L) & ~ref.fixed_nodes(33, 33)
+    assert not np.array_equal(out[orig], m[orig])
+    sub = m[4:13, 12:21]                     # the shifted subdomain around the crosspoint (8, 16)
+    alone = ref.perona_malik(sub, dt * 16, k / 4, steps)
+    assert np.array_equal(out[4:13, 12:21], alone)
