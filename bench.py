@@ -547,7 +547,9 @@ def main():
             "unit": "G SIMD issue-cycles/s",
             "frac": achieved / ISSUE_PEAK_G if achieved else None,
             "traffic": traffic_from_profile(args.workload),
-            "kernel": "walk_kernel<%s,%s>" % ("float" if cfg["prec"] == "fp32" else "double", kind),
+            "kernel": "walk_kernel<%s, %s, end-of-step exit%s>" % (
+                "float" if cfg["prec"] == "fp32" else "double", kind,
+                ", pipelined Philox" if cfg["prec"] == "fp32" and cfg["dt"] < 2e-5 else ""),
             "cycles_per_wave_step": per_step,
             "fp32_tflops": tflops,
             "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,
