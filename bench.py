@@ -147,20 +147,27 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
         arrivals = workloads.poisson_arrivals(n_requests, rate, seed=seed)
         out, pending = [], {}
         start = time.perf_counter()
+
+        def done(r):
+            out.append(r)
+            if len(out) % 100 == 0:
+                print(f"[serve] {len(out)} of {n_requests} requests done, "
+                      f"{time.perf_counter() - start:.0f} s", file=sys.stderr, flush=True)
+
         for req, ta in zip(reqs[burst:], arrivals):
             while True:
                 now = time.perf_counter() - start
                 for rid in list(pending):
                     r = srv.poll(rid)
                     if r is not None:
-                        out.append(r)
+                        done(r)
                         del pending[rid]
                 if now >= ta:
                     break
                 time.sleep(min(ta - now, 0.002))
             pending[srv.submit(req)] = True
         for rid in list(pending):
-            out.append(srv.wait(rid))
+            done(srv.wait(rid))
         wall = max(r["t_done"] for r in out) - min(r["t_submit"] for r in out)
     finally:
         srv.close()
@@ -421,6 +428,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / measured capacity")
     ap.add_argument("--serve-burst", type=int, default=16, help="requests of the capacity burst")
+    ap.add_argument("--serve-sweep", default="", metavar="LOADS",
+                    help="only run the serving stream at each load in LOADS (e.g. 0.5,0.8,1.0), one line each")
     ap.add_argument("--serve-bridge-dt", type=float, default=0.0,
                     help="> 0: serving requests use the bridge exit test at this time step")
     ap.add_argument("--bias-sweep", action="store_true",
@@ -451,6 +460,14 @@ def main():
                           tuple(args.sweep_exit.split(",")))
         print(json.dumps({"bias_sweep": rows, "paths_per_node": args.sweep_paths, "nodes": 64,
                           "workload": "sin2_bias_sweep"}), flush=True)
+        return
+
+    if args.serve_sweep:
+        import paper_1310_3435_amd as sdd
+        ctx = sdd.Context(0)
+        for load in (float(v) for v in args.serve_sweep.split(",")):
+            r = serve_stream(ctx, args.serve_requests, load, args.serve_burst, bridge_dt=args.serve_bridge_dt)
+            print(json.dumps({"serve": r}), flush=True)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -38,10 +38,10 @@ def test_result_is_the_same_alone_and_in_a_mix(ctx):
         say("serve: target alone")
         alone = srv.wait(srv.submit(target))
         assert alone["status"] == 0
-        mix = W.serving_requests(24, master_seed=9, grids=(33, 65), splits=(2, 4))
-        ids = [srv.submit(r) for r in mix[:12]]
+        mix = W.serving_requests(50, master_seed=9, grids=(33, 65), splits=(2, 4))
+        ids = [srv.submit(r) for r in mix[:25]]
         tid = srv.submit(target)
-        ids += [srv.submit(r) for r in mix[12:]]
+        ids += [srv.submit(r) for r in mix[25:]]
         say(f"serve: target in a mix of {len(mix)}")
         res = [srv.wait(i) for i in ids]
         mixed = srv.wait(tid)
