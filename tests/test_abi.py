@@ -46,6 +46,11 @@ def test_host_only_entry_points_work_without_a_gpu():
     assert sdd.sdd_workspace_bytes(1521, 10000) > 0
     assert sdd.sdd_workspace_bytes(0, 10000) == 0
     assert sdd.sdd_subdomain_workspace_bytes({"nx": 65, "ny": 33, "sx": 2, "sy": 1}) > 65 * 33 * 16
+    import ctypes as C
+    L65 = sdd.make_layout({"nx": 65, "ny": 49, "sx": 4, "sy": 3})
+    assert L.sdd_quality_workspace_bytes(65, 49) > 0 and L.sdd_quality_workspace_bytes(1, 49) == 0
+    assert L.sdd_smooth_workspace_bytes(C.byref(L65)) == 65 * 49 * 16
+    assert L.sdd_smooth_interfaces_workspace_bytes(C.byref(L65)) >= (3 * 49 + 2 * 65) * 16
 
 
 def test_struct_layouts_match_the_header():
@@ -55,6 +60,8 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(sdd.sdd_bmap) == 8 + 64 + 8
     assert ctypes.sizeof(sdd.sdd_layout) == 16
     assert sdd.PATH_RECORD.itemsize == 32
+    # request: density, map, layout, 4 int32, dt, se_target, paths, seed, t_max
+    assert ctypes.sizeof(sdd.sdd_request) == (16 + 4 * 64) + (8 + 64 + 8) + 16 + 16 + 5 * 8
 
 
 def test_product_path_does_not_import_the_oracle():
