@@ -94,7 +94,7 @@ def lib():
         L.sddref_philox4x32_10.argtypes = [P, P, P]
         L.sddref_philox_many.argtypes = [C.c_int64, P, P, P]
         L.sddref_normals64.argtypes = [C.c_int64, P, P]
-        L.sddref_uniforms.argtypes = [C.c_int64, P, P]
+        L.sddref_block_uniforms.argtypes = [C.c_int64, P, P]
         L.sddref_density_eval.argtypes = [C.POINTER(RefDensity), C.c_int64, P, P, P]
         L.sddref_bmap_eval.argtypes = [C.POINTER(RefBmap), C.c_int64, P, P, P]
         L.sddref_exit_point.argtypes = [C.c_double] * 4 + [P, P]
@@ -179,17 +179,20 @@ def philox(ctr: np.ndarray, key) -> np.ndarray:
     return out
 
 
-def normals64(words: np.ndarray) -> np.ndarray:
-    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 2)
-    z = np.empty(words.shape, dtype=np.float64)
-    lib().sddref_normals64(words.shape[0], _ptr(words), _ptr(z))
+def normals64(fields: np.ndarray) -> np.ndarray:
+    """Box-Muller of 21-bit field pairs [n][2] (u = (b + 1/2) 2^-21)."""
+    fields = np.ascontiguousarray(fields, dtype=np.uint32).reshape(-1, 2)
+    z = np.empty(fields.shape, dtype=np.float64)
+    lib().sddref_normals64(fields.shape[0], _ptr(fields), _ptr(z))
     return z
 
 
-def uniforms(words: np.ndarray) -> np.ndarray:
-    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
-    u = np.empty(words.shape, dtype=np.float64)
-    lib().sddref_uniforms(words.shape[0], _ptr(words), _ptr(u))
+def block_uniforms(blocks: np.ndarray) -> np.ndarray:
+    """The six uniforms [n][6] of Philox blocks [n][4]: (u_a, u_b) of steps
+    3m, 3m+1, 3m+2."""
+    blocks = np.ascontiguousarray(blocks, dtype=np.uint32).reshape(-1, 4)
+    u = np.empty((blocks.shape[0], 6), dtype=np.float64)
+    lib().sddref_block_uniforms(blocks.shape[0], _ptr(blocks), _ptr(u))
     return u
 
 
@@ -213,9 +216,9 @@ def exit_point(p, q):
 
 
 def bridge_uniforms(words: np.ndarray) -> np.ndarray:
-    """Uniforms of the bridge test from word pairs [n][2] (the nine high bits
-    of each word)."""
-    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 2)
+    """Uniforms of the bridge test from words of the counter-word-3 = 1
+    blocks (the low 23 bits)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
     u = np.empty(words.shape[0], dtype=np.float64)
     lib().sddref_bridge_uniforms(words.shape[0], _ptr(words), _ptr(u))
     return u

@@ -22,16 +22,18 @@
  *
  * Readings where the paper is silent (the same readings bind the HIP path):
  *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
- *     counter = (step pair m, path p, node g, 0); step 2m uses words 0,1 and
- *     step 2m+1 uses words 2,3;
- *   - uniforms u = ((r mod 2^23) + 1/2) * 2^-23 (the low 23 bits of a word),
- *     exactly representable in both float and double; normals by Box-Muller,
+ *     counter = (block m, path p, node g, 0); block m serves steps 3m, 3m+1
+ *     and 3m+2 with two 21-bit fields each (block_fields below);
+ *   - uniforms u = (b + 1/2) * 2^-21 for a field b, exactly representable in
+ *     both float and double; normals by Box-Muller,
  *     (z_xi, z_eta) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b);
  *   - exit point: first crossing of the last step's segment with the square
  *     boundary, in double precision; ties go to xi=0, xi=1, eta=0, eta=1;
- *   - step cap ceil(t_max / dt) rounded up to an even count (a Philox block
- *     serves two steps); a capped path takes the boundary value at the
- *     nearest boundary point and is counted.
+ *   - step cap ceil(t_max / dt) rounded up to a multiple of three (whole
+ *     Philox blocks); a capped path takes the boundary value at the nearest
+ *     boundary point and is counted;
+ *   - the Brownian-bridge test of step 3m+j draws word j of the block with
+ *     counter (m, p, g, 1).
  */
 #include <math.h>
 #include <stdint.h>
@@ -83,12 +85,30 @@ void sddref_philox_many(int64_t n, const uint32_t* ctr, const uint32_t key[2], u
 
 /* ---------------------------------------------------------------- normals */
 
-static double uniform23(uint32_t r) { return ((double)(r & 0x7FFFFFu) + 0.5) * 0x1p-23; }
+/* The uniform fields of one Philox block (the paper asks only for parallel
+ * pseudo-random numbers, Sec. 2.2; reading): a block serves three steps
+ * with two 21-bit fields each.  Steps 3m and 3m+1 take the high 21 bits of
+ * words (0, 1) and (2, 3); step 3m+2 takes the low 11 bits of word 0 with
+ * the low 10 bits of word 1 above them, and likewise words 2 and 3.  Every
+ * bit of the block but bit 10 of words 1 and 3 is used once. */
+static void block_fields(const uint32_t r[4], int j, uint32_t* ba, uint32_t* bb)
+{
+    if (j < 2) {
+        *ba = r[2 * j] >> 11;
+        *bb = r[2 * j + 1] >> 11;
+    } else {
+        *ba = (r[0] & 0x7FFu) | ((r[1] & 0x3FFu) << 11);
+        *bb = (r[2] & 0x7FFu) | ((r[3] & 0x3FFu) << 11);
+    }
+}
+
+/* u = (b + 1/2) 2^-21 for a 21-bit field b: in (0, 1), exact in float. */
+static double uniform21(uint32_t b) { return ((double)b + 0.5) * 0x1p-21; }
 
 static void box_muller64(uint32_t ra, uint32_t rb, double* z0, double* z1)
 {
     const double two_pi = 6.283185307179586476925286766559;
-    double ua = uniform23(ra), ub = uniform23(rb);
+    double ua = uniform21(ra), ub = uniform21(rb);
     double radius = sqrt(-2.0 * log(ua));
     double angle = two_pi * ub;
     *z0 = radius * cos(angle);
@@ -98,23 +118,30 @@ static void box_muller64(uint32_t ra, uint32_t rb, double* z0, double* z1)
 static void box_muller32(uint32_t ra, uint32_t rb, float* z0, float* z1)
 {
     const float two_pi = 6.28318530717958647692f;
-    float ua = ((float)(ra & 0x7FFFFFu) + 0.5f) * 0x1p-23f;
-    float ub = ((float)(rb & 0x7FFFFFu) + 0.5f) * 0x1p-23f;
+    float ua = ((float)ra + 0.5f) * 0x1p-21f;
+    float ub = ((float)rb + 0.5f) * 0x1p-21f;
     float radius = sqrtf(-2.0f * logf(ua));
     float angle = two_pi * ub;
     *z0 = radius * cosf(angle);
     *z1 = radius * sinf(angle);
 }
 
-/* words[n][2] -> z[n][2] (double precision transform) */
-void sddref_normals64(int64_t n, const uint32_t* words, double* z)
+/* 21-bit field pairs [n][2] -> z[n][2] (double precision transform) */
+void sddref_normals64(int64_t n, const uint32_t* fields, double* z)
 {
-    for (int64_t i = 0; i < n; ++i) box_muller64(words[2 * i], words[2 * i + 1], z + 2 * i, z + 2 * i + 1);
+    for (int64_t i = 0; i < n; ++i) box_muller64(fields[2 * i], fields[2 * i + 1], z + 2 * i, z + 2 * i + 1);
 }
 
-void sddref_uniforms(int64_t n, const uint32_t* words, double* u)
+/* blocks [n][4] -> u[n][6]: (u_a, u_b) of steps 3m, 3m+1, 3m+2 */
+void sddref_block_uniforms(int64_t n, const uint32_t* blocks, double* u)
 {
-    for (int64_t i = 0; i < n; ++i) u[i] = uniform23(words[i]);
+    for (int64_t i = 0; i < n; ++i)
+        for (int j = 0; j < 3; ++j) {
+            uint32_t a, b;
+            block_fields(blocks + 4 * i, j, &a, &b);
+            u[6 * i + 2 * j] = uniform21(a);
+            u[6 * i + 2 * j + 1] = uniform21(b);
+        }
 }
 
 /* ---------------------------------------------------------------- density */
@@ -315,19 +342,15 @@ static int nearest_boundary(double px, double py, double* ex, double* ey)
 
 /* ------------------------------------------------------- bridge exit test */
 
-/* Uniform from the 9 high bits of each of the step's two words (18 bits):
- * u = (b + 1/2) 2^-18 with b = (ra >> 23) | (rb >> 23) << 9.  These bits are
- * not used by the normals, which take the low 23 bits. */
-static double bridge_uniform(uint32_t ra, uint32_t rb)
-{
-    uint32_t b = (ra >> 23) | ((rb >> 23) << 9);
-    return ((double)b + 0.5) * 0x1p-18;
-}
+/* The bridge test of step 3m+j draws word j of the Philox block with
+ * counter word 3 = 1 (the normals' blocks have 0 there), as the uniform
+ * u = ((q mod 2^23) + 1/2) 2^-23, exact in float and double. */
+static double bridge_uniform(uint32_t q) { return ((double)(q & 0x7FFFFFu) + 0.5) * 0x1p-23; }
 
-/* Bridge uniforms of n word pairs (test access). */
+/* Bridge uniforms of n words (test access). */
 void sddref_bridge_uniforms(int64_t n, const uint32_t* words, double* u)
 {
-    for (int64_t i = 0; i < n; ++i) u[i] = bridge_uniform(words[2 * i], words[2 * i + 1]);
+    for (int64_t i = 0; i < n; ++i) u[i] = bridge_uniform(words[i]);
 }
 
 /* Brownian-bridge exit test (the conditional exit probability within a step
@@ -399,7 +422,7 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
 {
     const double s = sqrt(2.0 * dt);
     double X = xi0, Y = eta0;
-    uint32_t r[4] = { 0, 0, 0, 0 };
+    uint32_t r[4] = { 0, 0, 0, 0 }, q[4] = { 0, 0, 0, 0 };
     int64_t k = 0;
     for (;;) {
         if (k == kmax) {
@@ -407,12 +430,17 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
             o->capped = 1;
             break;
         }
-        if ((k & 1) == 0) {
-            uint32_t ctr[4] = { (uint32_t)(k >> 1), (uint32_t)p, (uint32_t)g, 0u };
+        const int j = (int)(k % 3);
+        if (j == 0) {
+            uint32_t ctr[4] = { (uint32_t)(k / 3), (uint32_t)p, (uint32_t)g, 0u };
             sddref_philox4x32_10(ctr, key, r);
+            if (bridge) {
+                ctr[3] = 1u;
+                sddref_philox4x32_10(ctr, key, q);
+            }
         }
-        uint32_t ra = (k & 1) ? r[2] : r[0];
-        uint32_t rb = (k & 1) ? r[3] : r[1];
+        uint32_t ra, rb;
+        block_fields(r, j, &ra, &rb);
         double zx, zy, w, gx, gy;
         box_muller64(ra, rb, &zx, &zy);
         density64(d, X, Y, &w, &gx, &gy);
@@ -430,7 +458,7 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
             break;
         }
         if (bridge) {
-            int sb = bridge_exit64(X, Y, Xn, Yn, dt, bridge_uniform(ra, rb));
+            int sb = bridge_exit64(X, Y, Xn, Yn, dt, bridge_uniform(q[j]));
             if (sb >= 0) {
                 onto_side(sb, Xn, Yn, &o->exi, &o->eeta);
                 o->side = sb;
@@ -451,7 +479,7 @@ static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, dou
     const float s = (float)sqrt(2.0 * dt);
     const float dtf = (float)dt;
     float X = (float)xi0, Y = (float)eta0;
-    uint32_t r[4] = { 0, 0, 0, 0 };
+    uint32_t r[4] = { 0, 0, 0, 0 }, q[4] = { 0, 0, 0, 0 };
     int64_t k = 0;
     for (;;) {
         if (k == kmax) {
@@ -459,12 +487,17 @@ static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, dou
             o->capped = 1;
             break;
         }
-        if ((k & 1) == 0) {
-            uint32_t ctr[4] = { (uint32_t)(k >> 1), (uint32_t)p, (uint32_t)g, 0u };
+        const int j = (int)(k % 3);
+        if (j == 0) {
+            uint32_t ctr[4] = { (uint32_t)(k / 3), (uint32_t)p, (uint32_t)g, 0u };
             sddref_philox4x32_10(ctr, key, r);
+            if (bridge) {
+                ctr[3] = 1u;
+                sddref_philox4x32_10(ctr, key, q);
+            }
         }
-        uint32_t ra = (k & 1) ? r[2] : r[0];
-        uint32_t rb = (k & 1) ? r[3] : r[1];
+        uint32_t ra, rb;
+        block_fields(r, j, &ra, &rb);
         float zx, zy, w, gx, gy;
         box_muller32(ra, rb, &zx, &zy);
         density32(d, X, Y, &w, &gx, &gy);
@@ -482,7 +515,7 @@ static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, dou
             break;
         }
         if (bridge) {
-            int sb = bridge_exit32(X, Y, Xn, Yn, dtf, (float)bridge_uniform(ra, rb));
+            int sb = bridge_exit32(X, Y, Xn, Yn, dtf, (float)bridge_uniform(q[j]));
             if (sb >= 0) {
                 onto_side(sb, (double)Xn, (double)Yn, &o->exi, &o->eeta);
                 o->side = sb;
@@ -536,7 +569,7 @@ int sddref_interface_estimate(const ref_density* d, const ref_bmap* b, const dou
     }
     if (!(t_max > 0.0)) t_max = 8.0;
     int64_t kmax = (int64_t)ceil(t_max / dt);
-    kmax += kmax & 1;
+    kmax += (3 - kmax % 3) % 3;  /* a whole number of Philox blocks (three steps each) */
     const uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     int64_t tot_steps = 0, tot_capped = 0;
 #ifdef _OPENMP

@@ -5,7 +5,7 @@ both inside).
 * the probability and side of one step against brute-force simulated
   Brownian bridges (fine substeps with the continuity correction for
   discrete monitoring), near each kind of wall and in a corner;
-* the bridge uniform is built from the word bits the normals leave unused;
+* the bridge uniform comes from its own Philox block (counter word 3 = 1);
 * with the bridge, the mean exit time of Brownian motion (w = 1) matches the
   torsion function to O(dt) with no correction, where the plain end-of-step
   test is off by O(sqrt dt);
@@ -84,21 +84,20 @@ def test_bridge_probability_symmetries(ref):
     assert ref.bridge_exit_prob((1e-12, 0.5), (0.3, 0.5), 1e-3)[0] == pytest.approx(1.0, abs=1e-9)
 
 
-def test_bridge_uniform_uses_the_bits_the_normals_leave(ref):
-    # value: b = (a >> 23) | (c >> 23) << 9, u = (b + 1/2) 2^-18
-    w = np.array([[0xFF800000, 0x00800000], [0, 0], [0xFFFFFFFF, 0xFFFFFFFF], [0x007FFFFF, 0x007FFFFF]],
-                 dtype=np.uint32)
+def test_bridge_uniform_from_its_own_block(ref):
+    # value: u = ((q mod 2^23) + 1/2) 2^-23 of a word of the counter-word-3 = 1 block
+    w = np.array([0xFF800000, 0, 0xFFFFFFFF, 0x007FFFFF, 12345678], dtype=np.uint32)
     u = ref.bridge_uniforms(w)
-    assert list(u) == [1023.5 * 2**-18, 0.5 * 2**-18, (2**18 - 0.5) * 2**-18, 0.5 * 2**-18]
-    # the normals of a word pair ignore the nine high bits, the bridge uniform the low 23
+    f = 2.0**-23
+    assert list(u) == [0.5 * f, 0.5 * f, (2**23 - 0.5) * f, (2**23 - 0.5) * f, ((12345678 % 2**23) + 0.5) * f]
+    # its blocks are not the normals' blocks: word 3 of the counter differs
+    ctr = np.array([[5, 7, 9, 0], [5, 7, 9, 1]], dtype=np.uint32)
+    blk = ref.philox(ctr, [3, 0])
+    assert not np.any(blk[0] == blk[1])
+    # uniform on (0, 1), exact in float
     rng = np.random.default_rng(3)
-    a = rng.integers(0, 2**32, size=(4096, 2), dtype=np.uint64).astype(np.uint32)
-    b = a ^ rng.integers(0, 2**9, size=(4096, 2), dtype=np.uint64).astype(np.uint32) << np.uint32(23)
-    assert np.array_equal(ref.normals64(a), ref.normals64(b))
-    c = a ^ rng.integers(0, 2**23, size=(4096, 2), dtype=np.uint64).astype(np.uint32)
-    assert np.array_equal(ref.bridge_uniforms(a), ref.bridge_uniforms(c))
-    # uniform on (0, 1)
-    u = ref.bridge_uniforms(rng.integers(0, 2**32, size=(200000, 2), dtype=np.uint64).astype(np.uint32))
+    u = ref.bridge_uniforms(rng.integers(0, 2**32, size=200000, dtype=np.uint64).astype(np.uint32))
+    assert np.all((u > 0) & (u < 1)) and np.array_equal(u.astype(np.float32).astype(np.float64), u)
     assert abs(u.mean() - 0.5) < 4 * math.sqrt(1 / 12 / u.size)
     assert abs(u.var() - 1 / 12) < 2e-3
 
