@@ -35,14 +35,18 @@ sys.path.insert(0, ROOT)
 # measured shader clock; rounded): 2-operand VALU ops (add, sub, mul, max,
 # xor, compare) 2 cycles, 3-operand ops (fma, v_bitop3_b32, v_and_or_b32,
 # v_mad_u64_u32) 4 cycles, transcendentals (exp, log, sqrt, rsq, rcp, sin,
-# cos) 8 cycles; classes do not overlap.  Per step: half a Philox4x32-10
-# block (10 v_mad_u64_u32 + 10 v_bitop3_b32 = 80), two uniforms (2 and_or +
-# 2 add = 12), Box-Muller (4 transcendentals + 2 mul = 36), the drift (ring
-# 60, gauss 40, sech2 66, sin2 56), the update (4 fma = 16) and the exit
-# test (4 two-operand ops = 8).  Peak issue capacity: 256 CUs x 4 SIMDs x
-# 2.4 GHz.  The roofline fraction is the share of that capacity the
-# algorithm's instructions fill at the measured step rate.
-CYCLES_PER_WAVE_STEP = {"ring": 212, "gauss": 192, "sech2": 218, "sin2": 208}
+# cos) 8 cycles; classes do not overlap.  Per step: a third of a
+# Philox4x32-10 block (20 v_mad_u64_u32 + 20 v_bitop3_b32 = 160 per block,
+# which feeds three steps), two uniforms (per block: four 21-bit fields by
+# shift + and_or, two by and + shift on two words + or3, six subtractions:
+# 60, so 20 a step), Box-Muller (4 transcendentals + 2 mul = 36), the drift
+# (ring 60, gauss 40, sech2 66, sin2 56), the update (4 fma = 16) and the
+# exit test (4 two-operand ops = 8).  Peak issue capacity: 256 CUs x 4
+# SIMDs x 2.4 GHz.  The roofline fraction is the share of that capacity
+# the algorithm's instructions fill at the measured step rate.
+_STEP_COMMON = 160 / 3 + 20 + 36 + 16 + 8
+CYCLES_PER_WAVE_STEP = {k: _STEP_COMMON + d for k, d in
+                        {"ring": 60, "gauss": 40, "sech2": 66, "sin2": 56}.items()}
 ISSUE_PEAK_G = 256 * 4 * 2.4e9 / 1e9  # G SIMD-cycles/s
 # FP32 floating-point operations per step (FMA = 2, transcendental = 1).
 FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 38, "sin2": 36}
@@ -573,7 +577,7 @@ def main():
             "kernel": "walk_kernel<%s, %s, end-of-step exit%s>" % (
                 "float" if cfg["prec"] == "fp32" else "double", kind,
                 ", pipelined Philox" if cfg["prec"] == "fp32" and cfg["dt"] < 2e-5 else ""),
-            "cycles_per_wave_step": per_step,
+            "cycles_per_wave_step": round(per_step, 2) if per_step else None,
             "fp32_tflops": tflops,
             "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,
             "fp32_frac_of_78_6_unpacked": tflops / (FP32_PEAK_TFLOPS / 2) if tflops else None,

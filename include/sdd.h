@@ -148,10 +148,12 @@ void sdd_destroy(sdd_ctx* ctx);
  * arithmetic mean of Sec. 2.2, paths of eq. (7b) by Euler-Maruyama).
  *
  * Random numbers (the paper asks only for parallel pseudo-random numbers,
- * Sec. 2.2): Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
- * (m, p, g, 0) for step pair m of path p of node g (g = index in `nodes`);
- * steps 2m and 2m+1 take words (0,1) and (2,3).  Uniforms
- * u = ((r mod 2^23) + 1/2) 2^-23; normals by Box-Muller,
+ * Sec. 2.2): Philox4x32-10 with key (seed mod 2^32, seed >> 32).  The block
+ * of counter (m, p, g, 0) (path p of node g, g = index in `nodes`) serves
+ * steps 3m, 3m+1 and 3m+2 with words w0..w3 cut into six 21-bit fields:
+ * step 3m takes w0 >> 11 and w1 >> 11, step 3m+1 w2 >> 11 and w3 >> 11,
+ * step 3m+2 (w0 & 0x7ff) | (w1 & 0x3ff) << 11 and the same of (w2, w3).
+ * Uniforms u = (b + 1/2) 2^-21 (exact in float); normals by Box-Muller,
  * sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).  Path p is therefore the
  * same wherever and whenever it is walked.
  *
@@ -160,8 +162,8 @@ void sdd_destroy(sdd_ctx* ctx);
  * first step that ends on or outside the square; its exit point is the
  * first crossing of that step's segment with the boundary, computed in
  * double in both modes, and its value is the boundary map there.  A path
- * still inside after ceil(t_max/dt) steps, rounded up to an even count, is
- * capped: it takes the value at the nearest boundary point and is counted
+ * still inside after ceil(t_max/dt) steps, rounded up to a multiple of 3
+ * (whole Philox blocks), is capped: it takes the value at the nearest boundary point and is counted
  * in stats->capped.
  *
  * exit_test SDD_EXIT_BRIDGE adds, after a step P -> Q with both ends inside,
@@ -170,8 +172,8 @@ void sdd_destroy(sdd_ctx* ctx);
  * hits a wall it starts a and ends b away from with probability
  * exp(-a b / dt).  Per axis the nearer wall counts, and the step exits with
  * probability p_xi + p_eta - p_xi p_eta (computed as one fma), compared with
- * the uniform u = (b + 1/2) 2^-18, b = (r_a >> 23) | (r_b >> 23) << 9, from
- * the nine high bits of the step's two words (the normals use the low 23).
+ * a uniform from a block of its own: step 3m + j takes word j of the block
+ * of counter (m, p, g, 1), u = ((q mod 2^23) + 1/2) 2^-23.
  * A bridged exit leaves through the nearer wall of the axis with the larger
  * probability (xi on ties), at Q moved onto that wall; these decisions are
  * taken in the walk precision.  Its bias in the exit point is O(dt) where
@@ -184,7 +186,7 @@ void sdd_destroy(sdd_ctx* ctx);
  *   w, bmap      host structs (bmap->table, if any, is device memory)
  *   nodes        device [n_nodes][2], every point strictly inside (0,1)^2
  *   paths_per_node  N >= 1; paths path_begin .. path_begin+N-1 are walked
- *   dt           0 < dt < 1, and ceil(t_max/dt) < 2^28 - 2
+ *   dt           0 < dt < 1, and ceil(t_max/dt) < 2^28 - 3
  *   t_max        step cap in time units; <= 0 selects 8
  *   exit_test    sdd_exit_test
  *   mean         device [n][2]   sum / N

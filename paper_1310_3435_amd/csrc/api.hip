@@ -94,8 +94,8 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
     if (!(t_max > 0.0)) t_max = 8.0;
     if (!is_finite(t_max)) return SDD_EINVAL;
     double kd = ceil(t_max / dt);
-    if (!(kd >= 1.0) || kd >= (double)(kMaxSteps - 1)) return SDD_EINVAL;
-    kd += fmod(kd, 2.0);  // the cap is rounded up to an even step count
+    if (!(kd >= 1.0) || kd >= (double)(kMaxSteps - 2)) return SDD_EINVAL;
+    kd += fmod(3.0 - fmod(kd, 3.0), 3.0);  // a whole number of three-step Philox blocks
     const WalkWorkspace W = walk_workspace(n_nodes, paths_per_node, prec);
     if (ws_bytes < W.bytes) return SDD_ENOSPC;
     if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;

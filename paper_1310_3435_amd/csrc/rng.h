@@ -42,31 +42,51 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
-// Uniform from the low 23 bits of a word: u = ((r & 0x7fffff) + 1/2) 2^-23,
-// exact in float and double.  In float it is built as the bit pattern
-// 1 + m 2^-23 (one v_and_or_b32) minus (1 - 2^-24), an exact subtraction.
-__device__ __forceinline__ float uniform_f32(uint32_t r)
+// The uniforms of one Philox block (Sec. 2.2 asks only for parallel
+// pseudo-random numbers; reading): the block of counter (m, p, g, 0) serves
+// steps 3m, 3m+1, 3m+2 with two 21-bit fields each, u = (b + 1/2) 2^-21,
+// exact in float and double:
+//   step 3m:   hi(w0), hi(w1)      hi(w) = w >> 11
+//   step 3m+1: hi(w2), hi(w3)
+//   step 3m+2: lo(w0, w1), lo(w2, w3)   lo(w, v) = (w & 0x7ff) | (v & 0x3ff) << 11
+// In float the field becomes the mantissa of 1 + b 2^-21, and subtracting
+// 1 - 2^-22 is exact.
+__device__ __forceinline__ float field_hi(uint32_t w, float)
 {
-    return __uint_as_float((r & 0x007fffffu) | 0x3f800000u) - 0x1.fffffep-1f;
+    return __uint_as_float(((w >> 9) & 0x007ffffcu) | 0x3f800000u) - 0x1.fffff8p-1f;
 }
+__device__ __forceinline__ float field_lo(uint32_t w, uint32_t v, float)
+{
+    return __uint_as_float(((w & 0x7ffu) << 2) | ((v & 0x3ffu) << 13) | 0x3f800000u) - 0x1.fffff8p-1f;
+}
+__device__ __forceinline__ double field_hi(uint32_t w, double) { return ((double)(w >> 11) + 0.5) * 0x1p-21; }
+__device__ __forceinline__ double field_lo(uint32_t w, uint32_t v, double)
+{
+    return ((double)((w & 0x7ffu) | ((v & 0x3ffu) << 11)) + 0.5) * 0x1p-21;
+}
+
+// Uniform of the bridge test from a word of the block with counter word 3
+// = 1: u = ((q & 0x7fffff) + 1/2) 2^-23, exact in float and double; in
+// float one v_and_or_b32 and an exact subtraction.
+__device__ __forceinline__ float uniform23(uint32_t q, float)
+{
+    return __uint_as_float((q & 0x007fffffu) | 0x3f800000u) - 0x1.fffffep-1f;
+}
+__device__ __forceinline__ double uniform23(uint32_t q, double) { return ((double)(q & 0x007fffffu) + 0.5) * 0x1p-23; }
 
 // Box-Muller pair (z0, z1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
 // The float version returns the pair scaled by 1/sqrt(2 ln 2),
 // sqrt(-log2 u_a) (cos, sin), and the caller folds sqrt(2 ln 2) into the
 // step's noise factor; v_sin/v_cos take their argument in turns.
-__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, float& z0, float& z1)
+__device__ __forceinline__ void normals(float ua, float ub, float& z0, float& z1)
 {
-    const float ua = uniform_f32(ra);
-    const float ub = uniform_f32(rb);
     const float radius = __builtin_amdgcn_sqrtf(-__builtin_amdgcn_logf(ua));
     z0 = radius * __builtin_amdgcn_cosf(ub);
     z1 = radius * __builtin_amdgcn_sinf(ub);
 }
 
-__device__ __forceinline__ void normals(uint32_t ra, uint32_t rb, double& z0, double& z1)
+__device__ __forceinline__ void normals(double ua, double ub, double& z0, double& z1)
 {
-    const double ua = ((double)(ra & 0x007fffffu) + 0.5) * 0x1p-23;
-    const double ub = ((double)(rb & 0x007fffffu) + 0.5) * 0x1p-23;
     const double radius = sqrt(-2.0 * log(ua));
     double sn, cs;
     sincos(kTwoPi * ub, &sn, &cs);
@@ -92,34 +112,25 @@ __device__ __forceinline__ bool outside(double x, double y) { return x <= 0.0 ||
 // is an independent one-dimensional bridge with diffusion coefficient 2, and
 // one that starts a and ends b away from a wall hits it within dt with
 // probability exp(-a b / dt); per axis the nearer wall counts, and the step
-// exits with probability p_xi + p_eta - p_xi p_eta.  The uniform compared
-// with it comes from the nine high bits of each of the step's two words,
-// which the normals do not use: u = (b + 1/2) 2^-18 with
-// b = (ra >> 23) | (rb >> 23) << 9.
+// exits with probability p_xi + p_eta - p_xi p_eta, compared with the
+// step's bridge uniform u (uniform23 above).
 //
-// Float: c = -log2(e) / dt, and u is built as the bit pattern 1 + b 2^-18
-// minus (1 - 2^-19), an exact subtraction.
-__device__ __forceinline__ bool bridge_exit(float px, float py, float qx, float qy, uint32_t ra, uint32_t rb,
-                                            float c)
+// Float: c = -log2(e) / dt.
+__device__ __forceinline__ bool bridge_exit(float px, float py, float qx, float qy, float u, float c)
 {
     const float mx = __builtin_fminf(px * qx, (1.0f - px) * (1.0f - qx));
     const float my = __builtin_fminf(py * qy, (1.0f - py) * (1.0f - qy));
     const float pxi = __builtin_amdgcn_exp2f(mx * c), peta = __builtin_amdgcn_exp2f(my * c);
-    const float p = __builtin_fmaf(-pxi, peta, pxi + peta);
-    const uint32_t bits = ((ra >> 18) & 0x00003fe0u) | ((rb >> 9) & 0x007fc000u) | 0x3f800000u;
-    return __uint_as_float(bits) - 0x1.fffffcp-1f < p;
+    return u < __builtin_fmaf(-pxi, peta, pxi + peta);
 }
 
 // Double: c = dt.
-__device__ __forceinline__ bool bridge_exit(double px, double py, double qx, double qy, uint32_t ra, uint32_t rb,
-                                            double c)
+__device__ __forceinline__ bool bridge_exit(double px, double py, double qx, double qy, double u, double c)
 {
     const double m0 = px * qx, m1 = (1.0 - px) * (1.0 - qx);
     const double m2 = py * qy, m3 = (1.0 - py) * (1.0 - qy);
     const double pxi = exp(-(m0 <= m1 ? m0 : m1) / c), peta = exp(-(m2 <= m3 ? m2 : m3) / c);
-    const double p = __builtin_fma(-pxi, peta, pxi + peta);
-    const uint32_t b = (ra >> 23) | ((rb >> 23) << 9);
-    return ((double)b + 0.5) * 0x1p-18 < p;
+    return u < __builtin_fma(-pxi, peta, pxi + peta);
 }
 
 // Side a bridged exit leaves through: the nearer wall of the axis with the

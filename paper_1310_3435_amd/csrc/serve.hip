@@ -96,10 +96,11 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
     uint64_t rec = 0;
     uint32_t g = 0, pc = 0;
     float X = 0, Y = 0;
-    int32_t k = 0;
+    uint32_t m = 0;  // Philox block index: steps 3m .. 3m+2
     // the lane's request
     float fbase = 1, dt = 0, sd = 0, bc = 0;
-    int32_t nterm = 0, kmax = 0;
+    int32_t nterm = 0;
+    uint32_t mmax = 0;  // step cap in blocks
     bool bridge = false;
     uint32_t key0 = 0, key1 = 0;
     float cx[kServeTerms], cy[kServeTerms], k2[kServeTerms], la[kServeTerms], m2c[kServeTerms];
@@ -150,12 +151,12 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
                 sd = R->noise;
                 bc = R->bridge_c;
                 bridge = R->bridge != 0;
-                kmax = R->kmax;
+                mmax = (uint32_t)(R->kmax / 3);
                 key0 = R->key0;
                 key1 = R->key1;
                 X = (float)R->nodes[2 * (size_t)g];
                 Y = (float)R->nodes[2 * (size_t)g + 1];
-                k = 0;
+                m = 0;
                 live = true;
             }
             pool_lo += take;
@@ -163,16 +164,14 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
         }
         if (__ballot(live) == 0) break;
 
-        const uint4 r = philox((uint32_t)(k >> 1), pc, g, 0u, key0, key1);
-        float z0, z1, bx, by;
-        float XA, YA, XB, YB;
-        {
-            normals(r.x, r.y, z0, z1);
+        const uint4 r = philox(m, pc, g, 0u, key0, key1);
+        // one Euler-Maruyama step of the lane's Gaussian-sum density
+        auto em = [&](float x, float y, float z0, float z1, float& xn, float& yn) {
             float W = fbase, Gx = 0.0f, Gy = 0.0f;
 #pragma unroll
             for (int q = 0; q < kServeTerms; ++q) {
                 if (q < nterm) {
-                    const float dx = X - cx[q], dy = Y - cy[q];
+                    const float dx = x - cx[q], dy = y - cy[q];
                     const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(k2[q], __builtin_fmaf(dx, dx, dy * dy), la[q]));
                     W += e;
                     const float h = m2c[q] * e;
@@ -181,54 +180,44 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
                 }
             }
             const float iw = __builtin_amdgcn_rcpf(W);
-            bx = Gx * iw;
-            by = Gy * iw;
-            XA = fmar(sd, z0, fmar(bx, dt, X));
-            YA = fmar(sd, z1, fmar(by, dt, Y));
-        }
-        {
-            normals(r.z, r.w, z0, z1);
-            float W = fbase, Gx = 0.0f, Gy = 0.0f;
-#pragma unroll
-            for (int q = 0; q < kServeTerms; ++q) {
-                if (q < nterm) {
-                    const float dx = XA - cx[q], dy = YA - cy[q];
-                    const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(k2[q], __builtin_fmaf(dx, dx, dy * dy), la[q]));
-                    W += e;
-                    const float h = m2c[q] * e;
-                    Gx = __builtin_fmaf(h, dx, Gx);
-                    Gy = __builtin_fmaf(h, dy, Gy);
-                }
-            }
-            const float iw = __builtin_amdgcn_rcpf(W);
-            bx = Gx * iw;
-            by = Gy * iw;
-            XB = fmar(sd, z0, fmar(bx, dt, XA));
-            YB = fmar(sd, z1, fmar(by, dt, YA));
-        }
+            xn = fmar(sd, z0, fmar(Gx * iw, dt, x));
+            yn = fmar(sd, z1, fmar(Gy * iw, dt, y));
+        };
+        float z0, z1, XA, YA, XB, YB, XC, YC;
+        normals(field_hi(r.x, 0.0f), field_hi(r.y, 0.0f), z0, z1);
+        em(X, Y, z0, z1, XA, YA);
+        normals(field_hi(r.z, 0.0f), field_hi(r.w, 0.0f), z0, z1);
+        em(XA, YA, z0, z1, XB, YB);
+        normals(field_lo(r.x, r.y, 0.0f), field_lo(r.z, r.w, 0.0f), z0, z1);
+        em(XB, YB, z0, z1, XC, YC);
+
         const bool outA = outside(XA, YA);
         const bool outB = outside(XB, YB);
-        bool exA = outA, exB = outB;
+        const bool outC = outside(XC, YC);
+        bool exA = outA, exB = outB, exC = outC;
         if (__ballot(live && bridge) != 0) {
             // some lane's request asks for the bridge test (wave-uniform branch)
-            exA = outA || (bridge && bridge_exit(X, Y, XA, YA, r.x, r.y, bc));
-            exB = outB || (bridge && bridge_exit(XA, YA, XB, YB, r.z, r.w, bc));
+            const uint4 q = philox(m, pc, g, 1u, key0, key1);
+            exA = outA || (bridge && bridge_exit(X, Y, XA, YA, uniform23(q.x, 0.0f), bc));
+            exB = outB || (bridge && bridge_exit(XA, YA, XB, YB, uniform23(q.y, 0.0f), bc));
+            exC = outC || (bridge && bridge_exit(XB, YB, XC, YC, uniform23(q.z, 0.0f), bc));
         }
-        const bool fin = live && (exA || exB || (k + 2 >= kmax));
+        const bool fin = live && (exA || exB || exC || (m + 1u >= mmax));
         if (fin) {
-            const float px = exA ? X : XA, py = exA ? Y : YA, qx = exA ? XA : XB, qy = exA ? YA : YB;
+            const float px = exA ? X : (exB ? XA : XB), py = exA ? Y : (exB ? YA : YB);
+            const float qx = exA ? XA : (exB ? XB : XC), qy = exA ? YA : (exB ? YB : YC);
             pq[rec] = make_float4(px, py, qx, qy);
-            uint32_t w = (uint32_t)(exA ? k + 1 : k + 2);
-            if (!(exA || exB))
+            uint32_t w = 3u * m + (exA ? 1u : (exB ? 2u : 3u));
+            if (!(exA || exB || exC))
                 w |= kInfoCapped;
-            else if (!(exA ? outA : outB))
+            else if (!(exA ? outA : (exB ? outB : outC)))
                 w |= kInfoBridged | (bridge_side(px, py, qx, qy) << kInfoSideShift);
             info[rec] = w;
             live = false;
         }
-        X = XB;
-        Y = YB;
-        k += 2;
+        X = XC;
+        Y = YC;
+        ++m;
     }
 }
 
@@ -496,7 +485,7 @@ sdd_status check_request(const sdd_server* S, const sdd_request* q, int64_t& n_n
     if (!(q->dt > 0.0) || !(q->dt < 1.0)) return SDD_EINVAL;
     if (!(q->se_target > 0.0) && q->paths_per_node < 2) return SDD_EINVAL;
     const double tmax = q->t_max > 0.0 ? q->t_max : 8.0;
-    if (!is_finite(tmax) || ceil(tmax / q->dt) >= (double)(kMaxSteps - 1)) return SDD_EINVAL;
+    if (!is_finite(tmax) || ceil(tmax / q->dt) >= (double)(kMaxSteps - 2)) return SDD_EINVAL;
     if (q->exit_test != SDD_EXIT_END_OF_STEP && q->exit_test != SDD_EXIT_BRIDGE) return SDD_EINVAL;
     const sdd_layout& L = q->layout;
     n_nodes = (int64_t)(L.sx - 1) * (L.sy - 1) + (int64_t)q->k * ((int64_t)(L.sx - 1) * L.sy + (int64_t)(L.sy - 1) * L.sx);
@@ -526,7 +515,7 @@ void fill_serve_req(const sdd_request& q, const double* nodes, uint32_t n_nodes,
     R.bridge = q.exit_test == SDD_EXIT_BRIDGE ? 1 : 0;
     const double tmax = q.t_max > 0.0 ? q.t_max : 8.0;
     double kd = ceil(tmax / q.dt);
-    kd += fmod(kd, 2.0);
+    kd += fmod(3.0 - fmod(kd, 3.0), 3.0);  // a whole number of three-step Philox blocks
     R.kmax = (int32_t)kd;
     R.key0 = (uint32_t)q.seed;
     R.key1 = (uint32_t)(q.seed >> 32);

@@ -4,8 +4,8 @@
 // device counter, 64 at a time per wave.  One lane walks one path; when its
 // path exits, the lane takes the wave's next ticket, whatever node it
 // belongs to, so lanes stay busy until the ticket range is exhausted.  A
-// loop iteration is one Philox block, i.e. two Euler-Maruyama steps (Sec.
-// 2.2) with an exit test after each; a path always starts at an even step.
+// loop iteration is one Philox block, i.e. three Euler-Maruyama steps (Sec.
+// 2.2) with an exit test after each; a path always starts a block.
 // With the Brownian-bridge option the step also exits, with the bridge's
 // conditional probability, when both its ends are inside (rng.h).
 // At exit the lane stores the last step's endpoints P, Q and the step count
@@ -74,7 +74,7 @@ constexpr int kWalkBlock = 256;
 __device__ __forceinline__ float bridge_const(const WalkArgs& A, float) { return (float)(-1.4426950408889634 / A.dt); }
 __device__ __forceinline__ double bridge_const(const WalkArgs& A, double) { return A.dt; }
 
-// PIPE: each iteration also computes the next pair's Philox block (it
+// PIPE: each iteration also computes the next three steps' Philox block (it
 // depends on the counters only), so that the waves left at the end of the
 // launch have independent work to overlap with the steps' latency; a new
 // path then computes its first block when it starts.  The random numbers,
@@ -94,9 +94,10 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
     // lane state
     bool live = false;
     uint32_t t = 0, g = 0, pc = 0;  // ticket, node, path counter word
-    uint4 rc = make_uint4(0, 0, 0, 0);  // Philox block of the lane's current step pair
+    uint4 rc = make_uint4(0, 0, 0, 0);  // Philox block of the lane's current three steps
     R X = 0, Y = 0;
-    int32_t k = 0;
+    uint32_t m = 0;                    // Philox block index: steps 3m .. 3m+2
+    const uint32_t mmax = (uint32_t)(A.kmax / 3);
 
     for (;;) {
         // hand the wave's tickets to idle lanes, in lane order
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
                 if (nx0 > 0.0 && nx0 < 1.0 && ny0 > 0.0 && ny0 < 1.0) {
                     X = (R)nx0;
                     Y = (R)ny0;
-                    k = 0;
+                    m = 0;
                     live = true;
                     if constexpr (PIPE) rc = philox(0u, pc, g, 0u, A.key0, A.key1);
                 } else {
@@ -144,49 +145,59 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
         uint4 r;
         if constexpr (PIPE) {
             r = rc;
-            rc = philox((uint32_t)(k >> 1) + 1u, pc, g, 0u, A.key0, A.key1);
+            rc = philox(m + 1u, pc, g, 0u, A.key0, A.key1);
         } else {
-            r = philox((uint32_t)(k >> 1), pc, g, 0u, A.key0, A.key1);
+            r = philox(m, pc, g, 0u, A.key0, A.key1);
         }
         R bx, by, z0, z1;
-        // step 2m
-        normals(r.x, r.y, z0, z1);
+        // step 3m
+        normals(field_hi(r.x, R(0)), field_hi(r.y, R(0)), z0, z1);
         drift<KIND>(A.dens, X, Y, bx, by);
         const R XA = fmar(sd, z0, fmar(bx, dt, X));
         const R YA = fmar(sd, z1, fmar(by, dt, Y));
-        // step 2m+1
-        normals(r.z, r.w, z0, z1);
+        // step 3m+1
+        normals(field_hi(r.z, R(0)), field_hi(r.w, R(0)), z0, z1);
         drift<KIND>(A.dens, XA, YA, bx, by);
         const R XB = fmar(sd, z0, fmar(bx, dt, XA));
         const R YB = fmar(sd, z1, fmar(by, dt, YA));
+        // step 3m+2
+        normals(field_lo(r.x, r.y, R(0)), field_lo(r.z, r.w, R(0)), z0, z1);
+        drift<KIND>(A.dens, XB, YB, bx, by);
+        const R XC = fmar(sd, z0, fmar(bx, dt, XB));
+        const R YC = fmar(sd, z1, fmar(by, dt, YB));
 
-        // the step cap is even, so it can only fall after step 2m+1
+        // the step cap is a whole number of blocks, so it can only fall
+        // after step 3m+2
         const bool outA = outside(XA, YA);
         const bool outB = outside(XB, YB);
-        bool exA = outA, exB = outB;
+        const bool outC = outside(XC, YC);
+        bool exA = outA, exB = outB, exC = outC;
         if constexpr (BRIDGE) {
-            exA = outA || bridge_exit(X, Y, XA, YA, r.x, r.y, bc);
-            exB = outB || bridge_exit(XA, YA, XB, YB, r.z, r.w, bc);
+            const uint4 q = philox(m, pc, g, 1u, A.key0, A.key1);
+            exA = outA || bridge_exit(X, Y, XA, YA, uniform23(q.x, R(0)), bc);
+            exB = outB || bridge_exit(XA, YA, XB, YB, uniform23(q.y, R(0)), bc);
+            exC = outC || bridge_exit(XB, YB, XC, YC, uniform23(q.z, R(0)), bc);
         }
-        const bool fin = live && (exA || exB || (k + 2 >= A.kmax));
+        const bool fin = live && (exA || exB || exC || (m + 1u >= mmax));
 
         if (fin) {
-            // the exit projection and boundary map run in the reduction
-            const R px = exA ? X : XA, py = exA ? Y : YA;
-            const R qx = exA ? XA : XB, qy = exA ? YA : YB;
+            // the first exiting step's ends; the exit projection and the
+            // boundary map run in the reduction
+            const R px = exA ? X : (exB ? XA : XB), py = exA ? Y : (exB ? YA : YB);
+            const R qx = exA ? XA : (exB ? XB : XC), qy = exA ? YA : (exB ? YB : YC);
             store_pq(A, t, px, py, qx, qy);
-            uint32_t w = (uint32_t)(exA ? k + 1 : k + 2);
-            if (!(exA || exB))
+            uint32_t w = 3u * m + (exA ? 1u : (exB ? 2u : 3u));
+            if (!(exA || exB || exC))
                 w |= kInfoCapped;
-            else if (BRIDGE && !(exA ? outA : outB))
+            else if (BRIDGE && !(exA ? outA : (exB ? outB : outC)))
                 w |= kInfoBridged | (bridge_side(px, py, qx, qy) << kInfoSideShift);
             A.info[t] = w;
             live = false;
         }
         // finished and idle lanes carry garbage until their next start
-        X = XB;
-        Y = YB;
-        k += 2;
+        X = XC;
+        Y = YC;
+        ++m;
     }
 }
 

@@ -183,7 +183,7 @@ def test_edge_cases(ctx, ref):
 def test_largest_ticket_count_and_empty_inputs(ctx, ref):
     """n * N just below the documented limit 2^32 - 2^24 (65280 nodes x 65535
     paths = 4.28e9 paths, 85.6 GB of per-path records in float), every path
-    capped at two steps; sampled nodes against the oracle's float walk.
+    capped at three steps (one Philox block); sampled nodes against the oracle's float walk.
     Then the limit itself, empty node lists and zero paths are rejected."""
     import ctypes as C
 
@@ -217,7 +217,7 @@ def test_largest_ticket_count_and_empty_inputs(ctx, ref):
     del ws
     torch.cuda.empty_cache()
     say(f"stats: steps {st[0]}, paths {st[1]}, capped {st[2]}")
-    assert st[1] == n * N and st[0] <= 2 * n * N and np.all(np.isfinite(m))
+    assert st[1] == n * N and st[0] <= 3 * n * N and np.all(np.isfinite(m))
     sample = np.array([0, 1234, n // 2, n - 1])
     r = ref.interface_estimate(d, {"kind": "identity"}, nodes[sample], N, 1e-3, 23, "fp32", t_max=1e-3,
                                node_ids=sample)
