@@ -107,31 +107,38 @@ __device__ __forceinline__ bool outside(float x, float y)
 }
 __device__ __forceinline__ bool outside(double x, double y) { return x <= 0.0 || x >= 1.0 || y <= 0.0 || y >= 1.0; }
 
-// Brownian-bridge exit test of one step P -> Q with both ends inside (the
-// conditional exit probability of Sec. 2.2).  Each coordinate of the bridge
-// is an independent one-dimensional bridge with diffusion coefficient 2, and
-// one that starts a and ends b away from a wall hits it within dt with
-// probability exp(-a b / dt); per axis the nearer wall counts, and the step
-// exits with probability p_xi + p_eta - p_xi p_eta, compared with the
-// step's bridge uniform u (uniform23 above).
+// Brownian-bridge exit probability of one step P -> Q with both ends
+// inside (the conditional exit probability of Sec. 2.2).  Each coordinate of
+// the bridge is an independent one-dimensional bridge with diffusion
+// coefficient 2, and one that starts a and ends b away from a wall hits it
+// within dt with probability exp(-a b / dt); per axis the nearer wall
+// counts, and the step exits with probability p_xi + p_eta - p_xi p_eta.
+// The step exits when its bridge uniform u (uniform23 above) is below it.
 //
 // Float: c = -log2(e) / dt.
-__device__ __forceinline__ bool bridge_exit(float px, float py, float qx, float qy, float u, float c)
+__device__ __forceinline__ float bridge_prob(float px, float py, float qx, float qy, float c)
 {
     const float mx = __builtin_fminf(px * qx, (1.0f - px) * (1.0f - qx));
     const float my = __builtin_fminf(py * qy, (1.0f - py) * (1.0f - qy));
     const float pxi = __builtin_amdgcn_exp2f(mx * c), peta = __builtin_amdgcn_exp2f(my * c);
-    return u < __builtin_fmaf(-pxi, peta, pxi + peta);
+    return __builtin_fmaf(-pxi, peta, pxi + peta);
 }
 
 // Double: c = dt.
-__device__ __forceinline__ bool bridge_exit(double px, double py, double qx, double qy, double u, double c)
+__device__ __forceinline__ double bridge_prob(double px, double py, double qx, double qy, double c)
 {
     const double m0 = px * qx, m1 = (1.0 - px) * (1.0 - qx);
     const double m2 = py * qy, m3 = (1.0 - py) * (1.0 - qy);
     const double pxi = exp(-(m0 <= m1 ? m0 : m1) / c), peta = exp(-(m2 <= m3 ? m2 : m3) / c);
-    return u < __builtin_fma(-pxi, peta, pxi + peta);
+    return __builtin_fma(-pxi, peta, pxi + peta);
 }
+
+// No bridge uniform is below 2^-24 (q = 0 gives (0 + 1/2) 2^-23), so a step
+// whose exit probability is at most 2^-24 never exits by the bridge, and
+// its uniform need not be drawn: a wave skips the bridge block when none of
+// its lanes has a larger probability.  The decisions are unchanged.
+template <typename R>
+__device__ __forceinline__ bool bridge_may_exit(R prob) { return prob > R(0x1p-24); }
 
 // Side a bridged exit leaves through: the nearer wall of the axis with the
 // larger probability, xi on ties (the walk's own precision decides).

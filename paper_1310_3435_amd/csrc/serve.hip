@@ -197,10 +197,17 @@ __global__ __launch_bounds__(256) void serve_walk_kernel(const ServeSeg* __restr
         bool exA = outA, exB = outB, exC = outC;
         if (__ballot(live && bridge) != 0) {
             // some lane's request asks for the bridge test (wave-uniform branch)
-            const uint4 q = philox(m, pc, g, 1u, key0, key1);
-            exA = outA || (bridge && bridge_exit(X, Y, XA, YA, uniform23(q.x, 0.0f), bc));
-            exB = outB || (bridge && bridge_exit(XA, YA, XB, YB, uniform23(q.y, 0.0f), bc));
-            exC = outC || (bridge && bridge_exit(XB, YB, XC, YC, uniform23(q.z, 0.0f), bc));
+            const float PA = bridge_prob(X, Y, XA, YA, bc);
+            const float PB = bridge_prob(XA, YA, XB, YB, bc);
+            const float PC = bridge_prob(XB, YB, XC, YC, bc);
+            const bool may = (!outA && bridge_may_exit(PA)) || (!outB && bridge_may_exit(PB)) ||
+                             (!outC && bridge_may_exit(PC));
+            if (__ballot(live && bridge && may) != 0) {
+                const uint4 q = philox(m, pc, g, 1u, key0, key1);
+                exA = outA || (bridge && uniform23(q.x, 0.0f) < PA);
+                exB = outB || (bridge && uniform23(q.y, 0.0f) < PB);
+                exC = outC || (bridge && uniform23(q.z, 0.0f) < PC);
+            }
         }
         const bool fin = live && (exA || exB || exC || (m + 1u >= mmax));
         if (fin) {

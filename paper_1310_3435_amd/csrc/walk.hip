@@ -173,10 +173,18 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
         const bool outC = outside(XC, YC);
         bool exA = outA, exB = outB, exC = outC;
         if constexpr (BRIDGE) {
-            const uint4 q = philox(m, pc, g, 1u, A.key0, A.key1);
-            exA = outA || bridge_exit(X, Y, XA, YA, uniform23(q.x, R(0)), bc);
-            exB = outB || bridge_exit(XA, YA, XB, YB, uniform23(q.y, R(0)), bc);
-            exC = outC || bridge_exit(XB, YB, XC, YC, uniform23(q.z, R(0)), bc);
+            const R PA = bridge_prob(X, Y, XA, YA, bc);
+            const R PB = bridge_prob(XA, YA, XB, YB, bc);
+            const R PC = bridge_prob(XB, YB, XC, YC, bc);
+            const bool may = (!outA && bridge_may_exit(PA)) || (!outB && bridge_may_exit(PB)) ||
+                             (!outC && bridge_may_exit(PC));
+            if (__ballot(live && may) != 0) {
+                // some lane is near a wall: draw the bridge block (wave-uniform branch)
+                const uint4 q = philox(m, pc, g, 1u, A.key0, A.key1);
+                exA = outA || uniform23(q.x, R(0)) < PA;
+                exB = outB || uniform23(q.y, R(0)) < PB;
+                exC = outC || uniform23(q.z, R(0)) < PC;
+            }
         }
         const bool fin = live && (exA || exB || exC || (m + 1u >= mmax));
 

@@ -128,6 +128,39 @@ def test_full_size_ring_workload_sampled_nodes(ctx, ref):
     assert np.mean(zs**2) < 1.3
 
 
+@pytest.mark.parametrize("exit_test", ["step", "bridge"])
+def test_pipelined_float_walk_paths_match_oracle(ctx, ref, exit_test):
+    """Float walks with dt < 2e-5 run the loop that computes the next Philox
+    block beside the current steps.  Ring density, nodes near the walls and a
+    cap of 501 steps (167 blocks), so that exits at every step of a block
+    and capped paths are both present; per path against the oracle's float
+    walk."""
+    c = W.cfg_ring_fp32()
+    rng = np.random.default_rng(31)
+    near = rng.uniform(0.005, 0.03, 6)
+    nodes = np.array([[near[0], 0.5], [1 - near[1], 0.4], [0.3, near[2]], [0.6, 1 - near[3]],
+                      [near[4], near[5]], [0.5, 0.5]])
+    dt, t_max, N = 1e-5, 5e-3, 300
+    g = gpu_estimate(ctx, c["density"], c["bmap"], nodes, N, dt, 41, "fp32", per_path=True, t_max=t_max,
+                     exit_test=exit_test)
+    r = ref.interface_estimate(c["density"], c["bmap"], nodes, N, dt, 41, "fp32", per_path=True, t_max=t_max,
+                               bridge=exit_test == "bridge")
+    gp, rp = g["per_path"], r["per_path"]
+    flips, dmax = compare_paths(gp, rp, 1e-5)
+    same = ~flips
+    d = np.maximum(np.abs(gp["exit_xi"] - rp["exit_xi"]), np.abs(gp["exit_eta"] - rp["exit_eta"]))[same]
+    q = np.percentile(d, [50, 99])
+    mod = np.bincount(rp["steps"][rp["capped"] == 0] % 3, minlength=3)
+    say(f"pipelined fp32 {exit_test}: flips {int(flips.sum())} of {flips.size}; capped {g['capped']} "
+        f"(oracle {r['capped']}); exit steps mod 3 {mod.tolist()}; diff p50 {q[0]:.2e} p99 {q[1]:.2e} max {dmax:.2e}")
+    assert g["capped"] > 0 and np.all(mod > 0)
+    assert flips.mean() < 2e-3
+    assert q[1] < 1e-5 and dmax < 1e-2
+    cap_same = (gp["capped"] == rp["capped"])
+    assert cap_same.mean() > 1 - 2e-3
+    assert np.all(gp["steps"][gp["capped"] == 1] == 501)
+
+
 def test_edge_cases(ctx, ref):
     import torch
 
