@@ -677,17 +677,17 @@ void decide_paths(sdd_server* S, Request* r)
     r->nb_total = (uint32_t)nb;
 }
 
+// Called once every block of the request is reduced: the launches that held
+// them have retired (their events, recorded after their reduces, have
+// completed), so the sums are final and the finish stream waits for nothing.
 void finish(sdd_server* S, Request* r)
 {
     hipStream_t st = S->finish_stream;
     const sdd_request& q = r->spec;
     const double paths = (double)r->nb_total * kBlockPaths;
-    hipError_t e = hipStreamWaitEvent(st, S->reduce_done, 0);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(serve_finalize_kernel, dim3((unsigned)((r->n_nodes + 255) / 256)), dim3(256), 0, st,
-                           r->acc, (uint32_t)r->n_nodes, paths, r->mean, r->se);
-        e = hipGetLastError();
-    }
+    hipLaunchKernelGGL(serve_finalize_kernel, dim3((unsigned)((r->n_nodes + 255) / 256)), dim3(256), 0, st,
+                       r->acc, (uint32_t)r->n_nodes, paths, r->mean, r->se);
+    hipError_t e = hipGetLastError();
     const Bmap B = to_device(&q.bmap);
     if (e == hipSuccess) e = launch_fill(q.layout, q.k, nullptr, B, r->nodes, r->mean, q.interp, r->vert, r->horiz, st);
     if (e == hipSuccess)
@@ -758,16 +758,15 @@ void worker_loop(sdd_server* S)
             Lh.busy = false;
             progress = true;
         }
-        // pilots: copy the sums to the host, then decide the paths
+        // pilots: copy the sums to the host, then decide the paths (the
+        // pilot block's launch has retired, so its sums are final)
         for (Request* r : std::vector<Request*>(S->active)) {
             if (r->state == PILOT && !r->cancelled && r->nb_done >= 1 && !r->pilot_copy) {
                 if (r->spec.se_target > 0.0) {
                     char* stage = S->pinned + (size_t)r->slot * S->slot_stride + align_up(sizeof(ServeReq), 256);
                     lk.unlock();
-                    hipError_t e = hipStreamWaitEvent(S->finish_stream, S->reduce_done, 0);
-                    if (e == hipSuccess)
-                        e = hipMemcpyAsync(stage, r->acc, (size_t)r->n_nodes * sizeof(NodeAcc), hipMemcpyDeviceToHost,
-                                           S->finish_stream);
+                    hipError_t e = hipMemcpyAsync(stage, r->acc, (size_t)r->n_nodes * sizeof(NodeAcc),
+                                                  hipMemcpyDeviceToHost, S->finish_stream);
                     if (e == hipSuccess) e = hipEventRecord(r->ev_pilot, S->finish_stream);
                     lk.lock();
                     if (e != hipSuccess) {
@@ -801,9 +800,10 @@ void worker_loop(sdd_server* S)
                     finish(S, r);
                     lk.lock();
                 } else {
+                    // every scheduled block has retired: nothing of the
+                    // request's is in flight, and its memory can go back
                     lk.unlock();
-                    hipError_t e = hipStreamWaitEvent(S->finish_stream, S->reduce_done, 0);
-                    if (e == hipSuccess) e = hipEventRecord(r->ev_done, S->finish_stream);
+                    (void)hipEventRecord(r->ev_done, S->finish_stream);
                     lk.lock();
                 }
                 r->state = FINISHING;
