@@ -41,6 +41,8 @@ const char* sdd_status_string(int status)
     case SDD_EINVAL: return "invalid argument";
     case SDD_ENOSPC: return "workspace too small";
     case SDD_EDEVICE: return "HIP runtime error";
+    case SDD_EAGAIN: return "not finished yet";
+    case SDD_ECANCELED: return "cancelled";
     case SDD_EUNSUPPORTED: return "unsupported";
     default: return "unknown status";
     }

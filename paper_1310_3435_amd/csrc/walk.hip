@@ -356,25 +356,28 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     // there are tickets.  More waves hide latency better but split the paths
     // over more lanes, and the last, longest paths then leave more lanes
     // idle; 4 measured best on the ring workload (2..8 swept).
-    static int per_cu_blocks = -1;
-    static int cus = 0;
-    if (per_cu_blocks < 0) {
+    struct Grid {
+        int per_cu_blocks, cus;
+    };
+    static const Grid grid = [] {  // once per instance (thread-safe initialisation)
+        Grid G{ 2, 256 };
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
+        if (hipDeviceGetAttribute(&G.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || G.cus <= 0)
+            G.cus = 256;
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, walk_kernel<R, KIND, BRIDGE, PIPE>, kWalkBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, walk_kernel<R, KIND, BRIDGE, PIPE>, kWalkBlock, 0) !=
+                hipSuccess ||
             occ <= 0)
             occ = 2;
         int want = 4;  // blocks of 4 waves: one wave per SIMD each
         const char* env = getenv("SDD_WALK_WAVES_PER_SIMD");
         if (env && atoi(env) > 0) want = atoi(env);
-        occ = want < occ ? want : occ;
-        per_cu_blocks = occ;
-    }
+        G.per_cu_blocks = want < occ ? want : occ;
+        return G;
+    }();
     const int64_t need = ((int64_t)A.total + kWave - 1) / kWave;
-    int64_t blocks = (int64_t)per_cu_blocks * cus;
+    int64_t blocks = (int64_t)grid.per_cu_blocks * grid.cus;
     const int64_t most = (need + kWalkBlock / kWave - 1) / (kWalkBlock / kWave);
     if (blocks > most) blocks = most;
     if (blocks < 1) blocks = 1;

@@ -38,6 +38,10 @@ def test_host_only_entry_points_work_without_a_gpu():
     L = sdd.lib()
     assert sdd.sdd_version() >= 100
     assert L.sdd_status_string(-1) == b"invalid argument"
+    # every status of the header has its own message
+    msgs = [L.sdd_status_string(c) for c in (0, -1, -2, -3, -4, -5, -6)]
+    assert len(set(msgs)) == 7 and b"unknown status" not in msgs
+    assert L.sdd_status_string(-99) == b"unknown status"
     assert sdd.sdd_layout_node_count({"nx": 257, "ny": 257, "sx": 4, "sy": 4}, 63) == 1521
     assert sdd.sdd_layout_node_count({"nx": 1025, "ny": 1025, "sx": 8, "sy": 8}, 32) == 3633
     assert sdd.sdd_layout_node_count({"nx": 65, "ny": 33, "sx": 2, "sy": 1}, 15) == 15
