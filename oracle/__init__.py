@@ -723,7 +723,8 @@ def pipeline(cfg: dict, nthreads: int = 0) -> dict:
     else:
         nodes = layout_nodes(L, cfg["k"], cfg.get("placement", "uniform"), dens)
     est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
-                             nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge", allow_off=True)
+                             t_max=cfg.get("t_max", 8.0), nthreads=nthreads,
+                             bridge=cfg.get("exit_test", "step") == "bridge", allow_off=True)
     vert, horiz = fill_interfaces(L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"), counts=counts)
     if cfg.get("smooth_span", 0) > 0:
         vert, horiz = smooth_interfaces(L, vert, horiz, int(cfg["smooth_span"]))

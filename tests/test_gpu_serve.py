@@ -166,3 +166,30 @@ def test_bridge_request_alone_in_a_mix_and_against_the_oracle(ctx, ref):
     say(f"served bridge vs oracle: double {diff:.3e}, float {d32:.3e} (SE {se:.3e}); bridge moved the mesh {shift:.3e}")
     assert diff <= 3 * se and d32 <= 0.5 * se
     assert shift > 3 * se          # at this dt the bridge changes the mesh well beyond the noise
+
+
+def test_capped_request_matches_the_oracle(ctx, ref):
+    """A step cap of 0.01 time units (102 steps at dt = 1e-4) stops most
+    paths: the serving walk's cap (whole Philox blocks) and the reduction's
+    nearest-boundary value for capped paths against the oracle's pipeline."""
+    import paper_1310_3435_amd as sdd
+    req = dict(small_request(seed=8, paths=2048, se=0.0), t_max=0.01)
+    srv = sdd.Server(ctx, hbm_budget_bytes=64 << 20, max_slots=4)
+    try:
+        say("serve: capped request")
+        out = srv.wait(srv.submit(req))
+    finally:
+        srv.close()
+    assert out["status"] == 0 and out["paths_per_node"] == 2048
+    cfg = dict(req, prec="fp32")
+    r32 = ref.pipeline(cfg)
+    est = r32["est"]
+    assert est["capped"] > 0.3 * est["paths"]
+    r64 = ref.pipeline(dict(cfg, prec="fp64"))
+    se = r64["est"]["se"].max()
+    d32 = np.abs(out["mesh"] - r32["mesh"]).max()
+    say(f"capped request: {est['capped']} of {est['paths']} oracle paths capped; steps {out['steps']} "
+        f"(oracle {est['steps']}); served vs oracle float pipeline {d32:.3e} (SE {se:.3e})")
+    assert out["steps"] == pytest.approx(est["steps"], rel=1e-4)
+    assert d32 <= 0.05 * se
+    assert np.abs(out["mesh"] - r64["mesh"]).max() <= 3 * se
