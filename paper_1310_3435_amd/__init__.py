@@ -12,6 +12,8 @@ built library or without a GPU the calls raise.
 from __future__ import annotations
 
 import ctypes as C
+import functools
+import inspect
 import os
 from typing import Optional, Tuple
 
@@ -211,6 +213,23 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
+def _on_stream(fn):
+    """Run an entry point with its ``stream`` argument as torch's current
+    stream, so that the outputs and workspaces it allocates belong to the
+    stream its kernels run on: torch then reuses a freed workspace only in
+    that stream's order."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapped(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        with _torch().cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return wrapped
+
+
 class Bmap:
     """Boundary map descriptor; a table map keeps its device table alive."""
 
@@ -246,14 +265,19 @@ class Context:
         h = C.c_void_p()
         _check(lib().sdd_create(device, C.byref(h)), "sdd_create")
         self.h = h
-        self._ws = None
+        self._ws = {}
 
     def workspace(self, nbytes: int):
-        """A reusable device workspace of at least nbytes."""
+        """A reusable device workspace of at least nbytes for the current
+        stream.  Calls on one stream run in order and share it; each stream
+        has its own, so calls on different streams do not overlap in it."""
         torch = _torch()
-        if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws
+        key = torch.cuda.current_stream().cuda_stream
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            self._ws[key] = ws
+        return ws
 
     def close(self):
         if self.h:
@@ -281,6 +305,7 @@ def sdd_workspace_bytes(n_nodes: int, paths_per_node: int, prec: str = "fp64") -
     return int(lib().sdd_workspace_bytes(int(n_nodes), int(paths_per_node), PREC[prec]))
 
 
+@_on_stream
 def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_node: int, dt: float, seed: int,
                            prec: str = "fp64", t_max: float = 8.0, path_begin: int = 0, want_se: bool = True,
                            want_sums: bool = False, want_stats: bool = True, per_path: bool = False,
@@ -338,6 +363,7 @@ def sdd_layout_node_count(layout: dict, k: int) -> int:
     return v
 
 
+@_on_stream
 def sdd_layout_nodes(ctx: Context, layout: dict, k: int, placement: str = "uniform",
                      density: Optional[dict] = None, stream=None):
     torch = _torch()
@@ -351,6 +377,7 @@ def sdd_layout_nodes(ctx: Context, layout: dict, k: int, placement: str = "unifo
     return nodes[:n]
 
 
+@_on_stream
 def sdd_layout_nodes_extrema(ctx: Context, layout: dict, density: dict, cap: int, stream=None):
     """(nodes, counts): crosspoints, then `cap` slots per segment holding the
     extrema of w_s and w_ss along it (Sec. 3.6); unused slots are (-1, -1)."""
@@ -367,6 +394,7 @@ def sdd_layout_nodes_extrema(ctx: Context, layout: dict, density: dict, cap: int
     return nodes[:n], counts[:nseg]
 
 
+@_on_stream
 def sdd_bmap_edge1d_table(ctx: Context, density: dict, n_per_edge: int = 4097, stream=None):
     torch = _torch()
     D = make_density(density)
@@ -376,6 +404,7 @@ def sdd_bmap_edge1d_table(ctx: Context, density: dict, n_per_edge: int = 4097, s
     return table
 
 
+@_on_stream
 def sdd_fill_interfaces(ctx: Context, layout: dict, k: int, bmap, nodes, values, interp: str = "linear",
                         stream=None, density: Optional[dict] = None, counts=None) -> Tuple[object, object]:
     """Interface lines from the node estimates; with `counts` (device int32)
@@ -403,6 +432,7 @@ def sdd_subdomain_workspace_bytes(layout: dict) -> int:
     return int(lib().sdd_subdomain_workspace_bytes(C.byref(L)))
 
 
+@_on_stream
 def sdd_subdomain_solve(ctx: Context, density: dict, bmap, layout: dict, vert, horiz, tol: float = 1e-13,
                         max_sweeps: int = 100000, stream=None, mesh=None) -> dict:
     torch = _torch()
@@ -428,6 +458,7 @@ def sdd_subdomain_solve(ctx: Context, density: dict, bmap, layout: dict, vert, h
 
 # ------------------------------------------------------ whole-grid mesh
 
+@_on_stream
 def sdd_grid_nodes(ctx: Context, nx: int, ny: int, stream=None):
     """Device float64 [(nx-2)(ny-2), 2]: every interior grid node, row by row."""
     torch = _torch()
@@ -436,6 +467,7 @@ def sdd_grid_nodes(ctx: Context, nx: int, ny: int, stream=None):
     return nodes
 
 
+@_on_stream
 def sdd_assemble_mesh(ctx: Context, nx: int, ny: int, bmap: "Bmap", values, stream=None):
     """Device mesh [ny, nx, 2]: boundary map on the ring, values inside."""
     torch = _torch()
@@ -445,6 +477,7 @@ def sdd_assemble_mesh(ctx: Context, nx: int, ny: int, bmap: "Bmap", values, stre
     return mesh
 
 
+@_on_stream
 def run_probabilistic(ctx: Context, cfg: dict, stream=None) -> dict:
     """The whole mesh by Monte Carlo at every interior node (Sec. 3.3) [->
     Perona-Malik smoothing of the whole grid (Sec. 3.4)], all on the GPU."""
@@ -464,6 +497,7 @@ def run_probabilistic(ctx: Context, cfg: dict, stream=None) -> dict:
 
 # ------------------------------------------------ quality and smoothing
 
+@_on_stream
 def sdd_mesh_quality(ctx: Context, mesh, want_cells: bool = False, stream=None) -> dict:
     """Q of every cell (eq. (11)) and {Q_max, Q_mean, folded} as device
     tensors: 'out' float64 [3], 'q' [ny-1, nx-1] if want_cells."""
@@ -478,6 +512,7 @@ def sdd_mesh_quality(ctx: Context, mesh, want_cells: bool = False, stream=None) 
     return {"out": out, "q": q}
 
 
+@_on_stream
 def sdd_mesh_compare(ctx: Context, density: dict, mesh, ref, stream=None):
     """Device float64 [2]: l_inf of the density at the nodes, largest node
     displacement."""
@@ -491,6 +526,7 @@ def sdd_mesh_compare(ctx: Context, density: dict, mesh, ref, stream=None):
     return out
 
 
+@_on_stream
 def sdd_mesh_smooth(ctx: Context, layout: dict, mesh, dt: float, k: float, steps: int, per_subdomain=True,
                     stream=None):
     """Perona-Malik FTCS smoothing of the device mesh [ny, nx, 2] in place (eq. (12)).
@@ -505,6 +541,7 @@ def sdd_mesh_smooth(ctx: Context, layout: dict, mesh, dt: float, k: float, steps
     return mesh
 
 
+@_on_stream
 def sdd_smooth_interfaces(ctx: Context, layout: dict, vert, horiz, span: int, stream=None):
     """Local quadratic regression of the device interface lines in place (Sec. 4)."""
     torch = _torch()
@@ -520,6 +557,7 @@ def sdd_smooth_interfaces(ctx: Context, layout: dict, vert, horiz, span: int, st
 
 # ------------------------------------------------------------ pipeline
 
+@_on_stream
 def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -> dict:
     """Nodes -> interface estimate -> fill [-> interface smoothing] ->
     subdomain solves [-> Perona-Malik smoothing], all on the GPU."""

@@ -161,6 +161,30 @@ def test_pipelined_float_walk_paths_match_oracle(ctx, ref, exit_test):
     assert np.all(gp["steps"][gp["capped"] == 1] == 501)
 
 
+def test_calls_on_side_streams_overlap_safely(ctx):
+    """Two estimates on two side streams through one context run at the same
+    time: each stream gets its own workspace, and each result is bitwise the
+    one its call gives alone on the default stream."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    d = W.random_density(19, 2)
+    bm = {"kind": "identity"}
+    na = torch.as_tensor(W.random_nodes(40, 3)).cuda()
+    nb = torch.as_tensor(W.random_nodes(70, 4)).cuda()
+    ref_a = sdd.sdd_interface_estimate(ctx, d, bm, na, 3000, 1e-3, 5, "fp64", want_sums=True)
+    ref_b = sdd.sdd_interface_estimate(ctx, d, bm, nb, 5000, 1e-3, 6, "fp32", want_sums=True)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    say("two estimates on two side streams")
+    a = sdd.sdd_interface_estimate(ctx, d, bm, na, 3000, 1e-3, 5, "fp64", want_sums=True, stream=s1)
+    b = sdd.sdd_interface_estimate(ctx, d, bm, nb, 5000, 1e-3, 6, "fp32", want_sums=True, stream=s2)
+    torch.cuda.synchronize()
+    for got, want in ((a, ref_a), (b, ref_b)):
+        assert torch.equal(got["mean"], want["mean"]) and torch.equal(got["sums"], want["sums"])
+        assert torch.equal(got["stats"], want["stats"])
+
+
 def test_edge_cases(ctx, ref):
     import torch
 
