@@ -711,15 +711,14 @@ size_t subdomain_workspace_bytes(const sdd_layout& L)
 
 static size_t lds_limit()
 {
-    static size_t lim = 0;
-    if (lim == 0) {
+    static const size_t lim = [] {  // once (thread-safe initialisation)
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
             v = 64 * 1024;
-        lim = (size_t)v;
-    }
+        return (size_t)v;
+    }();
     return lim;
 }
 
