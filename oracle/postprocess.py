@@ -59,12 +59,14 @@ def cell_jacobians(mesh: np.ndarray) -> np.ndarray:
 
 
 def quality_of(J: np.ndarray) -> np.ndarray:
-    """Q = tr(J^T J) / (2 sqrt(det(J^T J))), eq. (11)."""
+    """Q = tr(J^T J) / (2 sqrt(det(J^T J))), eq. (11).  A cell whose Jacobian
+    is singular (det = 0) has Q = inf, also a cell collapsed to a point
+    (J = 0), where the quotient is 0/0."""
     JtJ = np.einsum("...ki,...kj->...ij", J, J)
     tr = JtJ[..., 0, 0] + JtJ[..., 1, 1]
     det = JtJ[..., 0, 0] * JtJ[..., 1, 1] - JtJ[..., 0, 1] * JtJ[..., 1, 0]
     with np.errstate(divide="ignore", invalid="ignore"):
-        return 0.5 * tr / np.sqrt(det)
+        return np.where(det == 0.0, np.inf, 0.5 * tr / np.sqrt(det))
 
 
 def mesh_quality(mesh: np.ndarray) -> dict:

@@ -57,7 +57,9 @@ size_t post_workspace_bytes() { return (size_t)kPostMaxBlocks * 3 * sizeof(doubl
 // ---------------------------------------------------------------- quality
 
 // Q of one cell from its corners: J at the centre of the bilinear map,
-// Q = |J|_F^2 / (2 |det J|) (= tr(J^T J) / (2 sqrt(det J^T J))).
+// Q = |J|_F^2 / (2 |det J|) (= tr(J^T J) / (2 sqrt(det J^T J))); a cell
+// with det J = 0 has Q = inf, also when it has collapsed to a point (J = 0,
+// where the quotient is 0/0).
 __device__ __forceinline__ double cell_quality(const double2* m, int nx, int i, int j, double ihx, double ihy,
                                                double& detj)
 {
@@ -68,7 +70,7 @@ __device__ __forceinline__ double cell_quality(const double2* m, int nx, int i, 
     const double b = ((p01.x + p11.x) - (p00.x + p10.x)) * (0.5 * ihy);  // x_eta
     const double d = ((p01.y + p11.y) - (p00.y + p10.y)) * (0.5 * ihy);  // y_eta
     detj = a * d - b * c;
-    return 0.5 * (a * a + b * b + c * c + d * d) / fabs(detj);
+    return detj != 0.0 ? 0.5 * (a * a + b * b + c * c + d * d) / fabs(detj) : __builtin_inf();
 }
 
 __global__ __launch_bounds__(kPostBlock) void quality_kernel(const double2* __restrict__ mesh, int nx, int ny,

@@ -69,6 +69,14 @@ def test_quality_folds_and_degenerate_cells(ctx, ref):
     g = sdd.sdd_mesh_quality(ctx, dev(c))["out"].cpu().numpy()
     torch.cuda.synchronize()
     assert g[0] == np.inf and int(g[2]) == 1
+    # one cell of a grid collapsed to a point: Q = inf there, as in the oracle
+    m = noisy_mesh(9, 9, 2)
+    m[3:5, 3:5] = m[3, 3]
+    out = sdd.sdd_mesh_quality(ctx, dev(m), want_cells=True)
+    g, q = out["out"].cpu().numpy(), out["q"].cpu().numpy()
+    r = ref.mesh_quality(m)
+    assert q[3, 3] == np.inf and r["q"][3, 3] == np.inf and g[0] == np.inf
+    assert int(g[2]) == r["folded"]
 
 
 def test_compare_matches_oracle(ctx, ref):

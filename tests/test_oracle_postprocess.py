@@ -110,6 +110,10 @@ def test_quality_invariances_and_folds(ref):
     c = np.array([[[0.0, 0.0], [1.0, 0.0]], [[1.0, 0.0], [2.0, 0.0]]])
     r = ref.mesh_quality(c)
     assert r["q_max"] == np.inf and r["folded"] == 1
+    # a cell collapsed to a point (J = 0, Q = 0/0) is degenerate too
+    p = np.full((2, 2, 2), 0.3)
+    r = ref.mesh_quality(p)
+    assert r["q"][0, 0] == np.inf and r["q_max"] == np.inf and r["folded"] == 1
 
 
 def test_compare(ref):
