@@ -235,6 +235,14 @@ def test_edge_cases(ctx, ref):
             sdd.sdd_interface_estimate(ctx, d, bm, t, 10, args["dt"], 1, args["prec"])
     with pytest.raises(sdd.SddError):
         sdd.sdd_interface_estimate(ctx, {"base": -1.0, "terms": []}, bm, t, 10, 1e-3, 1)
+    # a step cap beyond the 28-bit step count, and path counters beyond 32 bits
+    with pytest.raises(sdd.SddError, match="invalid"):
+        sdd.sdd_interface_estimate(ctx, d, bm, t, 10, 1e-6, 1, t_max=300.0)
+    with pytest.raises(sdd.SddError, match="invalid"):
+        sdd.sdd_interface_estimate(ctx, d, bm, t, 10, 1e-3, 1, path_begin=2**32 - 5)
+    # the largest accepted cap: ceil(t_max/dt) = 2^28 - 4 rounds up to a whole block
+    g = gpu_estimate(ctx, d, bm, nodes, 64, 1e-3, 16, "fp32", t_max=(2**28 - 4) * 1e-3 * (1 - 1e-12))
+    assert g["capped"] == 0 and np.all(np.isfinite(g["mean"]))
 
 
 def test_largest_ticket_count_and_empty_inputs(ctx, ref):
