@@ -570,7 +570,8 @@ def run_pipeline(ctx: Context, cfg: dict, stream=None, per_path: bool = False) -
     else:
         nodes = sdd_layout_nodes(ctx, L, cfg["k"], cfg.get("placement", "uniform"), dens, stream=stream)
     est = sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
-                                 per_path=per_path, stream=stream, exit_test=cfg.get("exit_test", "step"))
+                                 t_max=cfg.get("t_max", 8.0), per_path=per_path, stream=stream,
+                                 exit_test=cfg.get("exit_test", "step"))
     vert, horiz = sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"),
                                       stream=stream, counts=counts)
     if cfg.get("smooth_span", 0) > 0:
