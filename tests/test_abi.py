@@ -74,3 +74,16 @@ def test_product_path_does_not_import_the_oracle():
     for f in os.listdir(os.path.join(ROOT, "paper_1310_3435_amd", "csrc")):
         s = open(os.path.join(ROOT, "paper_1310_3435_amd", "csrc", f)).read()
         assert "sddref" not in s and "oracle" not in s.lower()
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no fallback: without libsdd.so every entry point raises
+    import paper_1310_3435_amd as sdd
+    monkeypatch.setattr(sdd, "_lib", None)
+    monkeypatch.setattr(sdd, "LIB_PATH", os.path.join(ROOT, "no-such-dir", "libsdd.so"))
+    with pytest.raises(sdd.SddError, match="missing"):
+        sdd.lib()
+    with pytest.raises(sdd.SddError, match="missing"):
+        sdd.sdd_workspace_bytes(10, 10)
+    with pytest.raises(sdd.SddError, match="missing"):
+        sdd.sdd_layout_node_count({"nx": 65, "ny": 33, "sx": 2, "sy": 1}, 15)
