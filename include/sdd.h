@@ -53,7 +53,7 @@ typedef enum {
     SDD_EDEVICE = -3,      /* a HIP runtime call failed */
     SDD_EAGAIN = -4,       /* not finished yet (server poll) */
     SDD_ECANCELED = -5,    /* cancelled, or the server shut down first */
-    SDD_EUNSUPPORTED = -6  /* valid request this build does not implement */
+    SDD_EUNSUPPORTED = -6  /* a valid request of a kind the library does not implement */
 } sdd_status;
 
 typedef enum { SDD_FP64 = 0, SDD_FP32 = 1 } sdd_precision;
