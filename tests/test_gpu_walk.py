@@ -185,6 +185,47 @@ def test_calls_on_side_streams_overlap_safely(ctx):
         assert torch.equal(got["stats"], want["stats"])
 
 
+def test_full_size_annulus_workload_sampled_nodes(ctx, ref):
+    """The curved workload at full size (3633 equidistributed nodes x 1e5
+    paths, dt = 1e-5, float walk, shear-layer density, quarter-annulus map)
+    in the benchmark's launch configuration; eight sampled nodes against the
+    double-precision oracle."""
+    c = W.cfg_annulus_fp32()
+    nodes = ref.layout_nodes(c["layout"], c["k"], c["placement"], c["density"])
+    g = gpu_estimate(ctx, c["density"], c["bmap"], nodes, c["paths"], c["dt"], c["seed"], "fp32")
+    n = nodes.shape[0]
+    assert n == 3633 and g["paths"] == n * c["paths"] and g["capped"] == 0
+    assert np.all(np.isfinite(g["mean"]))
+    # maximum principle per component: the sector's boundary lies in [0, 2]^2
+    assert np.all((g["mean"] >= 0.0) & (g["mean"] <= 2.0))
+    sample = np.linspace(0, n - 1, 8).astype(int)
+    say(f"oracle fp64 on {len(sample)} sampled annulus nodes")
+    r = ref.interface_estimate(c["density"], c["bmap"], nodes[sample], c["paths"], c["dt"], c["seed"],
+                               node_ids=sample)
+    z = np.abs(g["mean"][sample] - r["mean"]) / r["se"]
+    say(f"annulus fp32 vs fp64 oracle sampled: max z {z.max():.3f}, max |diff| "
+        f"{np.abs(g['mean'][sample] - r['mean']).max():.3e}")
+    assert np.all(z <= 3.0)
+
+
+def test_bias_sweep_workload_full_paths_fp64(ctx, ref):
+    """The closed-form workload at its full 1e6 paths per node (dt = 1e-3,
+    1D edge data as the boundary map), double walk, three of its nodes:
+    path by path against the oracle."""
+    c = W.cfg_sin2_sweep()
+    nodes = np.array(c["nodes"])[[0, 31, 63]]
+    N = c["paths"]
+    g = gpu_estimate(ctx, c["density"], c["bmap"], nodes, N, 1e-3, c["seed"], "fp64", per_path=True)
+    r = ref.interface_estimate(c["density"], c["bmap"], nodes, N, 1e-3, c["seed"], per_path=True)
+    flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+    say(f"sin2 fp64, 3 x 1e6 paths: flips {int(flips.sum())}, max exit diff {dmax:.3e}, "
+        f"max mean diff {np.abs(g['mean'] - r['mean']).max():.3e}")
+    assert flips.mean() < 1e-5 and dmax <= 1e-12
+    # a flipped path moves its node's mean by at most 1/N of the map's range
+    bound = np.maximum(1e-10, flips.sum(axis=1)[:, None] / N)
+    assert np.all(np.abs(g["mean"] - r["mean"]) <= bound)
+
+
 def test_edge_cases(ctx, ref):
     import torch
 
