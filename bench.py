@@ -576,7 +576,8 @@ def main():
             "traffic": traffic_from_profile(args.workload),
             "kernel": "walk_kernel<%s, %s, end-of-step exit%s>" % (
                 "float" if cfg["prec"] == "fp32" else "double", kind,
-                ", pipelined Philox" if cfg["prec"] == "fp32" and cfg["dt"] < 2e-5 else ""),
+                ", pipelined Philox" if cfg["prec"] == "fp32" and cfg["dt"] < 2e-5 and kind in (None, "sech2", "sin2")
+                else ""),
             "cycles_per_wave_step": round(per_step, 2) if per_step else None,
             "fp32_tflops": tflops,
             "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,

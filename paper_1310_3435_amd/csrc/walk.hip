@@ -385,11 +385,13 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     return hipGetLastError();
 }
 
+// Single-term densities run a kernel specialised on their kind.
+inline int walk_kind(const WalkArgs& A) { return A.dens.n_terms == 1 ? A.dens.kind[0] : kAnyTerms; }
+
 template <typename R, bool BRIDGE, bool PIPE>
 static hipError_t launch_walk_kind(const WalkArgs& A, hipStream_t stream)
 {
-    const int kind = A.dens.n_terms == 1 ? A.dens.kind[0] : kAnyTerms;
-    switch (kind) {
+    switch (walk_kind(A)) {
     case SDD_TERM_GAUSS: return launch_walk_kernel<R, SDD_TERM_GAUSS, BRIDGE, PIPE>(A, stream);
     case SDD_TERM_RING: return launch_walk_kernel<R, SDD_TERM_RING, BRIDGE, PIPE>(A, stream);
     case SDD_TERM_SECH2: return launch_walk_kernel<R, SDD_TERM_SECH2, BRIDGE, PIPE>(A, stream);
@@ -398,17 +400,31 @@ static hipError_t launch_walk_kind(const WalkArgs& A, hipStream_t stream)
     }
 }
 
-// Float walks with small steps (paths of thousands of steps, where the end
-// of the launch is long) use the pipelined loop; the first-block cost of a
-// new path outweighs it below a few thousand steps (measured on the ring
-// workload: +2.4% at 1.2e4 steps per path, -1% at 1.7e3, -5% at 450).
+// Float walks with small steps may compute the next block's Philox beside
+// the current steps (PIPE).  Whether that pays depends on how the compiler
+// schedules each drift and exit test; measured same-box (1521 nodes,
+// steps/s, pipelined against plain loop):
+//
+//   dt = 1e-5      gauss   ring    sech^2  sin^2   sum of terms
+//   end of step    -1%     -4%     +5%     +7%     +1.5%
+//   bridge         -1.5%   +1.5%   -3%     -4%     +4%
+//
+// At dt = 1e-4 and 1e-3 it ties or loses for every kind (up to 9%).
 constexpr double kPipeMaxDt = 2e-5;
+
+inline bool pipe_pays(const WalkArgs& A)
+{
+    if (!(A.dt < kPipeMaxDt)) return false;
+    const int kind = walk_kind(A);
+    if (A.bridge) return kind == SDD_TERM_RING || kind == kAnyTerms;
+    return kind == SDD_TERM_SECH2 || kind == SDD_TERM_SIN2 || kind == kAnyTerms;
+}
 
 template <typename R>
 static hipError_t launch_walk_prec(const WalkArgs& A, hipStream_t stream)
 {
     if constexpr (sizeof(R) == sizeof(float)) {
-        if (A.dt < kPipeMaxDt)
+        if (pipe_pays(A))
             return A.bridge ? launch_walk_kind<R, true, true>(A, stream) : launch_walk_kind<R, false, true>(A, stream);
     }
     return A.bridge ? launch_walk_kind<R, true, false>(A, stream) : launch_walk_kind<R, false, false>(A, stream);

@@ -129,13 +129,16 @@ def test_full_size_ring_workload_sampled_nodes(ctx, ref):
 
 
 @pytest.mark.parametrize("exit_test", ["step", "bridge"])
-def test_pipelined_float_walk_paths_match_oracle(ctx, ref, exit_test):
-    """Float walks with dt < 2e-5 run the loop that computes the next Philox
-    block beside the current steps.  Ring density, nodes near the walls and a
-    cap of 501 steps (167 blocks), so that exits at every step of a block
-    and capped paths are both present; per path against the oracle's float
-    walk."""
-    c = W.cfg_ring_fp32()
+@pytest.mark.parametrize("kind", ["ring", "sech2"])
+def test_small_step_float_walk_paths_match_oracle(ctx, ref, kind, exit_test):
+    """Float walks at dt = 1e-5, where the loop that computes the next Philox
+    block beside the current steps runs for sech^2 without the bridge and
+    for the ring with it, and the plain loop otherwise.  Nodes near the
+    walls and a cap of 501 steps (167 blocks), so that exits at every step
+    of a block and capped paths are both present; per path against the
+    oracle's float walk."""
+    c = {"density": (W.cfg_ring_fp32() if kind == "ring" else W.cfg_annulus_fp32())["density"],
+         "bmap": {"kind": "identity"}}
     rng = np.random.default_rng(31)
     near = rng.uniform(0.005, 0.03, 6)
     nodes = np.array([[near[0], 0.5], [1 - near[1], 0.4], [0.3, near[2]], [0.6, 1 - near[3]],
@@ -151,7 +154,7 @@ def test_pipelined_float_walk_paths_match_oracle(ctx, ref, exit_test):
     d = np.maximum(np.abs(gp["exit_xi"] - rp["exit_xi"]), np.abs(gp["exit_eta"] - rp["exit_eta"]))[same]
     q = np.percentile(d, [50, 99])
     mod = np.bincount(rp["steps"][rp["capped"] == 0] % 3, minlength=3)
-    say(f"pipelined fp32 {exit_test}: flips {int(flips.sum())} of {flips.size}; capped {g['capped']} "
+    say(f"small-step fp32 {kind} {exit_test}: flips {int(flips.sum())} of {flips.size}; capped {g['capped']} "
         f"(oracle {r['capped']}); exit steps mod 3 {mod.tolist()}; diff p50 {q[0]:.2e} p99 {q[1]:.2e} max {dmax:.2e}")
     assert g["capped"] > 0 and np.all(mod > 0)
     assert flips.mean() < 2e-3
