@@ -482,7 +482,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(nodes and requests would shard across GPUs, one process each)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
