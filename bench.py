@@ -53,11 +53,18 @@ FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 38, "sin2": 36}
 FP32_PEAK_TFLOPS = 157.3
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(src_dir: str = None) -> str:
+    """Hash of the walk kernel's code (comments and layout removed), which
+    ties the committed counter figures to the kernel they were taken on."""
+    import re
+    src_dir = src_dir or os.path.join(ROOT, "paper_1310_3435_amd", "csrc")
     h = hashlib.sha256()
     for f in ("walk.hip", "walk.h", "common.h", "rng.h"):
-        with open(os.path.join(ROOT, "paper_1310_3435_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(src_dir, f)) as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -9,10 +9,11 @@
 // With the Brownian-bridge option the step also exits, with the bridge's
 // conditional probability, when both its ends are inside (rng.h).
 // At exit the lane stores the last step's endpoints P, Q and the step count
-// (with the side of a bridged exit) in the path's own slot.  A second kernel projects P -> Q onto the boundary
-// in double, evaluates the boundary map there (eq. (7a)) and reduces each
-// node's paths in a fixed order, so every result is independent of the
-// schedule, and the walk keeps no double-precision state.
+// (with the side of a bridged exit) in the path's own slot.  A second kernel
+// projects P -> Q onto the boundary in double, evaluates the boundary map
+// there (eq. (7a)) and reduces each node's paths in a fixed order, so every
+// result is independent of the schedule, and the walk keeps no
+// double-precision state.
 //
 // The walk itself touches HBM only to read a node at path start and to
 // write 20 bytes (float walk) or 36 bytes (double walk) per finished path.
@@ -78,7 +79,8 @@ __device__ __forceinline__ double bridge_const(const WalkArgs& A, double) { retu
 // depends on the counters only), so that the waves left at the end of the
 // launch have independent work to overlap with the steps' latency; a new
 // path then computes its first block when it starts.  The random numbers,
-// and hence all results, are the same either way.
+// and hence all results, are the same either way; which kernels it speeds
+// up is measured (launch_walk_prec).
 template <typename R, int KIND, bool BRIDGE, bool PIPE>
 __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
 {
