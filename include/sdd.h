@@ -31,8 +31,10 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls enqueue work and return after host-side validation; outputs are
  *     valid once the stream has been synchronised.
- *   - Return values: SDD_OK (0); negative values are errors and nothing was
- *     enqueued; no exception crosses the ABI.  sdd_status_string() names
+ *   - Return values: SDD_OK (0); negative values are errors; no exception
+ *     crosses the ABI.  Argument errors (SDD_EINVAL, SDD_ENOSPC) are found
+ *     before anything is enqueued; SDD_EDEVICE reports a failed HIP call,
+ *     after which the outputs are undefined.  sdd_status_string() names
  *     them.  A context is not thread-safe; use one per host thread.
  *   - Arrays of points are [n][2] doubles (xi, eta) or (x, y), row-major.
  */
