@@ -69,6 +69,9 @@ __device__ __forceinline__ void load_pq(const void* pq, size_t t, double, double
 }
 
 constexpr uint32_t kTicketBatch = 64;
+// Steps below this make paths of thousands of steps (the unit square's exit
+// time is O(0.1)); launch choices below are measured on either side of it.
+constexpr double kLongPathDt = 2e-5;
 constexpr int kWalkBlock = 256;
 
 // Constant of the bridge test: -log2(e)/dt in float, dt in double.
@@ -353,33 +356,35 @@ __global__ __launch_bounds__(1024) void stats_kernel(const long long* __restrict
 template <typename R, int KIND, bool BRIDGE, bool PIPE>
 static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
 {
-    // a persistent grid of 4 waves per SIMD (SDD_WALK_WAVES_PER_SIMD
+    // A persistent grid of a few waves per SIMD (SDD_WALK_WAVES_PER_SIMD
     // overrides; capped by what the device keeps resident), never more than
     // there are tickets.  More waves hide latency better but split the paths
     // over more lanes, and the last, longest paths then leave more lanes
-    // idle; 4 measured best on the ring workload (2..8 swept).
+    // idle.  Measured same-box: paths of thousands of steps (dt < 2e-5) run
+    // 1-2% faster with 3 than with 4 (ring, sin^2, sech^2), shorter paths
+    // 4.5% faster with 4; 2, 5, 6 and 8 are slower.
     struct Grid {
-        int per_cu_blocks, cus;
+        int occ, cus, env;
     };
     static const Grid grid = [] {  // once per instance (thread-safe initialisation)
-        Grid G{ 2, 256 };
+        Grid G{ 2, 256, 0 };
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&G.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || G.cus <= 0)
             G.cus = 256;
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, walk_kernel<R, KIND, BRIDGE, PIPE>, kWalkBlock, 0) !=
-                hipSuccess ||
-            occ <= 0)
-            occ = 2;
-        int want = 4;  // blocks of 4 waves: one wave per SIMD each
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&G.occ, walk_kernel<R, KIND, BRIDGE, PIPE>, kWalkBlock,
+                                                         0) != hipSuccess ||
+            G.occ <= 0)
+            G.occ = 2;
         const char* env = getenv("SDD_WALK_WAVES_PER_SIMD");
-        if (env && atoi(env) > 0) want = atoi(env);
-        G.per_cu_blocks = want < occ ? want : occ;
+        if (env && atoi(env) > 0) G.env = atoi(env);
         return G;
     }();
+    int want = A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one wave per SIMD each
+    if (grid.env > 0) want = grid.env;
+    const int per_cu_blocks = want < grid.occ ? want : grid.occ;
     const int64_t need = ((int64_t)A.total + kWave - 1) / kWave;
-    int64_t blocks = (int64_t)grid.per_cu_blocks * grid.cus;
+    int64_t blocks = (int64_t)per_cu_blocks * grid.cus;
     const int64_t most = (need + kWalkBlock / kWave - 1) / (kWalkBlock / kWave);
     if (blocks > most) blocks = most;
     if (blocks < 1) blocks = 1;
@@ -405,18 +410,17 @@ static hipError_t launch_walk_kind(const WalkArgs& A, hipStream_t stream)
 // Float walks with small steps may compute the next block's Philox beside
 // the current steps (PIPE).  Whether that pays depends on how the compiler
 // schedules each drift and exit test; measured same-box (1521 nodes,
-// steps/s, pipelined against plain loop):
+// steps/s, 4 waves per SIMD, pipelined against plain loop):
 //
 //   dt = 1e-5      gauss   ring    sech^2  sin^2   sum of terms
 //   end of step    -1%     -4%     +5%     +7%     +1.5%
 //   bridge         -1.5%   +1.5%   -3%     -4%     +4%
 //
 // At dt = 1e-4 and 1e-3 it ties or loses for every kind (up to 9%).
-constexpr double kPipeMaxDt = 2e-5;
 
 inline bool pipe_pays(const WalkArgs& A)
 {
-    if (!(A.dt < kPipeMaxDt)) return false;
+    if (!(A.dt < kLongPathDt)) return false;
     const int kind = walk_kind(A);
     if (A.bridge) return kind == SDD_TERM_RING || kind == kAnyTerms;
     return kind == SDD_TERM_SECH2 || kind == SDD_TERM_SIN2 || kind == kAnyTerms;
