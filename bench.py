@@ -133,7 +133,8 @@ def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int):
             "full_workload_s_extrapolated": full_steps / rate}
 
 
-def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, bridge_dt: float = 0.0):
+def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, bridge_dt: float = 0.0,
+                 launch_paths: int = 0):
     """Serving stream: a burst of `burst` requests measures capacity
     (requests/s at saturation); then `n_requests` arrive as a Poisson stream
     at `load` x capacity.  Latency = arrival (submit) to the mesh being in
@@ -147,7 +148,8 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
     reqs = workloads.serving_requests(n_requests + burst, master_seed=seed)
     if bridge_dt > 0:
         reqs = [dict(r, exit_test="bridge", dt=bridge_dt) for r in reqs]
-    srv = sdd.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=64, max_nodes=4096, max_points=257 * 257)
+    srv = sdd.Server(ctx, hbm_budget_bytes=4 << 30, max_slots=64, max_nodes=4096, max_points=257 * 257,
+                     launch_paths=launch_paths)
     try:
         t0 = srv.clock()
         ids = [srv.submit(r) for r in reqs[:burst]]
@@ -447,6 +449,8 @@ def main():
     ap.add_argument("--serve-burst", type=int, default=16, help="requests of the capacity burst")
     ap.add_argument("--serve-sweep", default="", metavar="LOADS",
                     help="only run the serving stream at each load in LOADS (e.g. 0.5,0.8,1.0), one line each")
+    ap.add_argument("--serve-launch-paths", type=int, default=0,
+                    help="paths per serving walk launch (0: the server's default)")
     ap.add_argument("--serve-bridge-dt", type=float, default=0.0,
                     help="> 0: serving requests use the bridge exit test at this time step")
     ap.add_argument("--bias-sweep", action="store_true",
@@ -483,7 +487,8 @@ def main():
         import paper_1310_3435_amd as sdd
         ctx = sdd.Context(0)
         for load in (float(v) for v in args.serve_sweep.split(",")):
-            r = serve_stream(ctx, args.serve_requests, load, args.serve_burst, bridge_dt=args.serve_bridge_dt)
+            r = serve_stream(ctx, args.serve_requests, load, args.serve_burst, bridge_dt=args.serve_bridge_dt,
+                             launch_paths=args.serve_launch_paths)
             print(json.dumps({"serve": r}), flush=True)
         return
 
@@ -616,7 +621,7 @@ def main():
                                      est["mean"].cpu().numpy(), args.bridge_paths)
     if args.serve_requests > 0:
         line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst,
-                                     bridge_dt=args.serve_bridge_dt)
+                                     bridge_dt=args.serve_bridge_dt, launch_paths=args.serve_launch_paths)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes, steps_per_pass)
     print(json.dumps(line), flush=True)
