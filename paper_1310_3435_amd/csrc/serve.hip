@@ -878,7 +878,10 @@ sdd_status sdd_server_create(sdd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_
         sdd_server_destroy(S);
         return SDD_EDEVICE;
     }
-    S->walk_blocks = std::max(1, std::min(occ, 4)) * cus;
+    int want = 4;  // waves per SIMD (blocks of 4 waves per CU); SDD_SERVE_WAVES_PER_SIMD overrides
+    if (const char* env = getenv("SDD_SERVE_WAVES_PER_SIMD"))
+        if (atoi(env) > 0) want = atoi(env);
+    S->walk_blocks = std::max(1, std::min(occ, want)) * cus;
     for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
     S->worker = std::thread(worker_loop, S);
     *out = S;

@@ -360,9 +360,11 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     // overrides; capped by what the device keeps resident), never more than
     // there are tickets.  More waves hide latency better but split the paths
     // over more lanes, and the last, longest paths then leave more lanes
-    // idle.  Measured same-box: paths of thousands of steps (dt < 2e-5) run
-    // 1-2% faster with 3 than with 4 (ring, sin^2, sech^2), shorter paths
-    // 4.5% faster with 4; 2, 5, 6 and 8 are slower.
+    // idle.  Measured same-box: a single-term kernel runs paths of thousands
+    // of steps (dt < 2e-5) 1-4% faster with 3 waves than with 4 (ring,
+    // sin^2, sech^2), shorter paths up to 4.5% faster with 4, and loses 2-4%
+    // with 6 or 8; the general sum of terms, whose term loop leaves more
+    // latency to hide, gains 14-21% from 4 to 8.
     struct Grid {
         int occ, cus, env;
     };
@@ -380,7 +382,7 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
         if (env && atoi(env) > 0) G.env = atoi(env);
         return G;
     }();
-    int want = A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one wave per SIMD each
+    int want = KIND == kAnyTerms ? 8 : A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one per SIMD
     if (grid.env > 0) want = grid.env;
     const int per_cu_blocks = want < grid.occ ? want : grid.occ;
     const int64_t need = ((int64_t)A.total + kWave - 1) / kWave;
