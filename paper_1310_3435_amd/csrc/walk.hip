@@ -415,17 +415,19 @@ static hipError_t launch_walk_kind(const WalkArgs& A, hipStream_t stream)
 // steps/s, 4 waves per SIMD, pipelined against plain loop):
 //
 //   dt = 1e-5      gauss   ring    sech^2  sin^2   sum of terms
-//   end of step    -1%     -4%     +5%     +7%     +1.5%
-//   bridge         -1.5%   +1.5%   -3%     -4%     +4%
+//   end of step    -1%     -4%     +5%     +7%     +1.5% (-2% at 8 waves)
+//   bridge         -1.5%   +1.5%   -3%     -4%     +4% (0 at 8 waves)
 //
-// At dt = 1e-4 and 1e-3 it ties or loses for every kind (up to 9%).
+// The sum of terms runs 8 waves per SIMD (launch_walk_kernel), where it no
+// longer pays.  At dt = 1e-4 and 1e-3 it ties or loses for every kind (up
+// to 9%).
 
 inline bool pipe_pays(const WalkArgs& A)
 {
     if (!(A.dt < kLongPathDt)) return false;
     const int kind = walk_kind(A);
-    if (A.bridge) return kind == SDD_TERM_RING || kind == kAnyTerms;
-    return kind == SDD_TERM_SECH2 || kind == SDD_TERM_SIN2 || kind == kAnyTerms;
+    if (A.bridge) return kind == SDD_TERM_RING;
+    return kind == SDD_TERM_SECH2 || kind == SDD_TERM_SIN2;
 }
 
 template <typename R>
