@@ -37,6 +37,9 @@
  *     after which the outputs are undefined.  sdd_status_string() names
  *     them.  A context is not thread-safe; use one per host thread.
  *   - Arrays of points are [n][2] doubles (xi, eta) or (x, y), row-major.
+ *   - Environment (tuning only; no result depends on it): SDD_WALK_WAVES_PER_SIMD
+ *     and SDD_SERVE_WAVES_PER_SIMD set the waves per SIMD of the walk's and
+ *     the server's persistent grids instead of the measured defaults.
  */
 #ifndef SDD_H
 #define SDD_H
