@@ -609,10 +609,16 @@ def main():
         ms64 = a.elapsed_time(b)
         st64 = int(e64["stats"].cpu().numpy()[0])
         se64 = float(np.median(e64["se"].cpu().numpy()))
+        # per node: the float walk's estimate against the double walk's (same paths)
+        d = np.abs(e64["mean"].cpu().numpy() - est["mean"].cpu().numpy())
+        z = d / np.maximum(e64["se"].cpu().numpy(), 1e-300)
+        q = lambda a: {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)),
+                       "max": float(a.max())}
         line["fp64_walk"] = {"walk_ms": ms64, "walk_steps_per_s": st64 / (ms64 / 1e3), "median_se": se64,
                              "fp32_speedup_at_equal_se": ms64 / float(np.mean(walk_ms)),
-                             "max_node_diff_fp32_vs_fp64": float(np.abs(e64["mean"].cpu().numpy() -
-                                                                        est["mean"].cpu().numpy()).max())}
+                             "max_node_diff_fp32_vs_fp64": float(d.max()),
+                             "node_diff_fp32_vs_fp64": q(d), "node_diff_over_se": q(z),
+                             "nodes": int(d.shape[0])}
     if not args.no_quality:
         line["quality"] = quality_study(ctx, cfg, B, nodes, est["mean"], sol["mesh"])
         line["paper_example"] = paper_study(ctx)
