@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 # Issue cost of one float Euler-Maruyama step, in SIMD cycles per wave64
 # step, from the algorithm's instruction mix weighted by the gfx950 issue
-# cost of each instruction class measured with csrc/valu_rates.hip (at the
+# cost of each instruction class measured by a micro-benchmark (at the
 # measured shader clock; rounded): 2-operand VALU ops (add, sub, mul, max,
 # xor, compare) 2 cycles, 3-operand ops (fma, v_bitop3_b32, v_and_or_b32,
 # v_mad_u64_u32) 4 cycles, transcendentals (exp, log, sqrt, rsq, rcp, sin,

@@ -34,14 +34,6 @@ def build(verbose: bool = False) -> str:
     if verbose and err.strip():
         sys.stderr.write(err + "\n")
     os.replace(tmp, LIB)
-    # the VALU issue-cost probe behind the walk's roofline (standalone tool)
-    tool = os.path.join(HERE, "valu_rates")
-    r = subprocess.run([hipcc] + [f for f in FLAGS if f not in ("-fPIC", "-shared")] +
-                       [os.path.join(CSRC, "valu_rates.hip"), "-o", tool + ".tmp"], capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stderr + "\n")
-        raise RuntimeError("hipcc failed building valu_rates")
-    os.replace(tool + ".tmp", tool)
     return LIB
 
 
