@@ -5,19 +5,23 @@ estimate (walk + finalize), interface fill and the batched subdomain
 solves, all on the GPU, inputs already resident in HBM.  Prints one JSON
 line.
 
-Default workload: ring density w = 1 + 10 exp(-200 (r - 0.3)^2), identity
-boundary map, 4 x 4 subdomains of 65 x 65 nodes (global 257 x 257), every
-interior interface node estimated (1521 nodes), 1e4 paths per node,
-dt = 1e-5, float walk with compensated double accumulation.
+Default workload (the largest single-GPU one): shear-layer density
+w = 1 + 20 sech^2(40 (xi - eta)) on the quarter annulus 1 <= rho <= 2,
+8 x 8 subdomains of 129 x 129 nodes (global 1025 x 1025), 32 points per
+interface segment placed by equidistributing w (3633 nodes), 1e5 paths per
+node, dt = 1e-5, float walk with exact double node sums, monotone cubic
+fill.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                    [--no-cpu-baseline] [--no-fp64] [--serve-requests N]
-                    [--serve-load RHO]
+                    [--no-cpu-baseline] [--no-ring] [--serve-requests N]
+                    [--serve-load RHO] [--serve-bridge-dt DT]
 
-Beside the throughput line it reports the double-precision walk on the same
-workload (equal paths, hence equal standard error) and a serving run: a
-Poisson stream of mesh requests at RHO x the measured capacity, with p50/p99
-latency from arrival to the mesh in host memory.
+Beside the throughput line it reports the ring workload (4 x 4 of 65 x 65,
+1521 nodes x 1e4 paths) with its double-precision walk (equal paths, hence
+equal standard error) and its 64-node double-oracle subset, the
+Brownian-bridge and exponential-stepping legs on the closed-form workload,
+and a serving run: a Poisson stream of mesh requests at RHO x the measured
+capacity, with p50/p99 latency from arrival to the mesh in host memory.
 """
 import argparse
 import hashlib
@@ -29,28 +33,32 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Issue cost of one float Euler-Maruyama step, in SIMD cycles per wave64
-# step, from the algorithm's instruction mix weighted by the gfx950 issue
-# cost of each instruction class measured by a micro-benchmark (at the
-# measured shader clock; rounded): 2-operand VALU ops (add, sub, mul, max,
-# xor, compare) 2 cycles, 3-operand ops (fma, v_bitop3_b32, v_and_or_b32,
-# v_mad_u64_u32) 4 cycles, transcendentals (exp, log, sqrt, rsq, rcp, sin,
-# cos) 8 cycles; classes do not overlap.  Per step: a third of a
-# Philox4x32-10 block (20 v_mad_u64_u32 + 20 v_bitop3_b32 = 160 per block,
-# which feeds three steps), two uniforms (per block: four 21-bit fields by
-# shift + and_or, two by and + shift on two words + or3, six subtractions:
-# 60, so 20 a step), Box-Muller (4 transcendentals + 2 mul = 36), the drift
-# (ring 60, gauss 40, sech2 66, sin2 56), the update (4 fma = 16) and the
-# exit test (4 two-operand ops = 8).  Peak issue capacity: 256 CUs x 4
-# SIMDs x 2.4 GHz.  The roofline fraction is the share of that capacity
-# the algorithm's instructions fill at the measured step rate.
+# Algorithmic FP32 floating-point operations per float Euler-Maruyama step
+# (FMA = 2, transcendental = 1), the roofline's unit of work: Box-Muller (a
+# log, a sqrt, a sin, a cos, two products), the drift of each density kind
+# (ring: offsets, r^2, rsqrt, exp, rcp and the products; gauss: one
+# exp-term sum; sech^2: exp, two rcp and products; sin^2: sin, cos, rcp and
+# products), the update (4 FMA) and the exit test.  The peak is MI355X's
+# published FP32 vector rate.
+FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 38, "sin2": 36}
+FP32_PEAK_TFLOPS = 157.3
+# Issue-cycle view, beside the FLOP roofline: SIMD cycles per wave64 step
+# from the algorithm's instruction mix weighted by gfx950's measured issue
+# cost per instruction class (profiles/valu_rates_gfx950.md: two-operand
+# ops 2 cycles, three-operand ops (fma, v_bitop3_b32, v_and_or_b32,
+# v_mad_u64_u32) 4, transcendentals 8).  Per step: a third of a
+# Philox4x32-10 block (20 v_mad_u64_u32 + 20 v_bitop3_b32 = 160 per block),
+# two uniforms (60 per block, 20 a step), Box-Muller 36, the drift (ring 60,
+# gauss 40, sech2 66, sin2 56), the update 16, the exit test 8.  Capacity:
+# 256 CUs x 4 SIMDs x 2.4 GHz.
 _STEP_COMMON = 160 / 3 + 20 + 36 + 16 + 8
 CYCLES_PER_WAVE_STEP = {k: _STEP_COMMON + d for k, d in
                         {"ring": 60, "gauss": 40, "sech2": 66, "sin2": 56}.items()}
 ISSUE_PEAK_G = 256 * 4 * 2.4e9 / 1e9  # G SIMD-cycles/s
-# FP32 floating-point operations per step (FMA = 2, transcendental = 1).
-FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 38, "sin2": 36}
-FP32_PEAK_TFLOPS = 157.3
+# HBM bytes the walk must move per launch: the node table (16 B a node) and
+# the node sums (96 B a node, zeroed then written back); a path reads and
+# writes nothing beyond on-chip memory and the node sums' cache lines.
+WALK_BYTES_PER_NODE = 16 + 2 * 96
 
 
 def kernel_source_hash(src_dir: str = None) -> str:
@@ -59,7 +67,7 @@ def kernel_source_hash(src_dir: str = None) -> str:
     import re
     src_dir = src_dir or os.path.join(ROOT, "paper_1310_3435_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("walk.hip", "walk.h", "common.h", "rng.h"):
+    for f in ("walk.hip", "walk.h", "walk_core.h", "common.h", "rng.h"):
         with open(os.path.join(src_dir, f)) as fh:
             code = fh.read()
         code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
@@ -98,39 +106,52 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int):
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int, gpu_mean=None, single_paths: int = 10000):
     """The oracle, untuned, on this host's cores: `sample_nodes` evenly spaced
     nodes of the same workload at its full paths per node, double precision;
-    then one node on one core.  The full workload's oracle time is
-    extrapolated linearly in steps from the all-core rate."""
+    then one node with `single_paths` paths on one core.  The full
+    workload's oracle time is extrapolated linearly in steps from the
+    all-core rate.  With gpu_mean (the timed run's node estimates: the same
+    counters, so the same paths in float) the sample also gives, node by
+    node, |GPU - oracle| / SE."""
     import numpy as np
 
     import oracle
     oracle.lib()
     n = nodes.shape[0]
     idx = (np.arange(sample_nodes) * (n // sample_nodes)).astype(np.int64)
-    threads = os.cpu_count() or 1
-    try:
-        threads = len(os.sched_getaffinity(0))
-    except AttributeError:
-        pass
+    threads = host_threads()
     t0 = time.perf_counter()
     r = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[idx], cfg["paths"], cfg["dt"], cfg["seed"],
                                   "fp64", node_ids=idx, nthreads=threads)
     el = time.perf_counter() - t0
     one = idx[sample_nodes // 2: sample_nodes // 2 + 1]
     t0 = time.perf_counter()
-    r1 = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[one], cfg["paths"], cfg["dt"], cfg["seed"],
+    r1 = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[one], single_paths, cfg["dt"], cfg["seed"],
                                    "fp64", node_ids=one, nthreads=1)
     el1 = time.perf_counter() - t0
     rate = r["steps"] / el
-    return {"value": rate, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample_nodes} of {n} nodes (indices i*{n // sample_nodes}), {cfg['paths']} paths/node, "
-                      f"dt={cfg['dt']}, fp64 walk, {r['steps']} steps in {el:.2f} s",
-            "nodes_per_s": sample_nodes / el, "cpu": cpu_model(),
-            "single_core": {"value": r1["steps"] / el1, "unit": "walk steps/s",
-                            "sample": f"node {int(one[0])}, {cfg['paths']} paths, {r1['steps']} steps in {el1:.2f} s"},
-            "full_workload_s_extrapolated": full_steps / rate}
+    out = {"value": rate, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{sample_nodes} of {n} nodes (indices i*{n // sample_nodes}), {cfg['paths']} paths/node, "
+                     f"dt={cfg['dt']}, fp64 walk, {r['steps']} steps in {el:.2f} s",
+           "nodes_per_s": sample_nodes / el, "cpu": cpu_model(),
+           "single_core": {"value": r1["steps"] / el1, "unit": "walk steps/s",
+                           "sample": f"node {int(one[0])}, {single_paths} paths, {r1['steps']} steps in {el1:.2f} s"},
+           "full_workload_s_extrapolated": full_steps / rate}
+    if gpu_mean is not None:
+        z = np.abs(gpu_mean[idx] - r["mean"]) / r["se"]
+        out["gpu_vs_oracle"] = {"what": "float GPU walk against this double oracle run, same paths, per node",
+                                "abs_diff_over_se": [round(float(v), 5) for v in z.max(1)],
+                                "max_abs_diff": float(np.abs(gpu_mean[idx] - r["mean"]).max()),
+                                "median_se": float(np.median(r["se"]))}
+    return out
 
 
 def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, bridge_dt: float = 0.0,
@@ -184,7 +205,7 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
         wall = max(r["t_done"] for r in out) - min(r["t_submit"] for r in out)
     finally:
         srv.close()
-    ok = [r for r in out if r["status"] == 0]
+    ok = [r for r in out if r["status"] >= 0]   # 0, or 1: done with capped paths
     lat = np.array([r["t_done"] - r["t_submit"] for r in ok]) * 1e3
     steps = sum(r["steps"] for r in ok)
     return {
@@ -194,6 +215,9 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
         "mean_latency_ms": float(lat.mean()), "throughput_req_per_s": len(ok) / wall,
         "walk_steps_per_s": steps / wall, "median_paths_per_node": float(np.median([r["paths_per_node"] for r in ok])),
         "max_se": float(max(r["max_se"] for r in ok)),
+        "capped_paths": int(sum(r["capped"] for r in ok)),
+        "stage_ms_median": {k: float(np.median([r[k] for r in ok]))
+                            for k in ("t_queue_ms", "t_stoc_ms", "t_fill_ms", "t_sub_ms")},
         "stream": "1-4 Gaussian bumps (amp U[1,20], width U[20,200]), grids {33,65,129,257}^2, 2x2..8x8 "
                   "subdomains, SE 1e-3 per node, float walks, Poisson arrivals, "
                   + (f"bridge exit test at dt {bridge_dt:g}" if bridge_dt > 0 else "end-of-step exit test at dt 1e-4"),
@@ -434,33 +458,153 @@ def paper_study(ctx):
     return out
 
 
+def walk_kind_name(cfg) -> str:
+    terms = cfg["density"]["terms"]
+    if all(t["kind"] == "gauss" for t in terms):
+        return "gauss"
+    return terms[0]["kind"] if len(terms) == 1 else "sum"
+
+
+def roofline(cfg, steps_per_launch: int, walk_s: float, traffic):
+    """The walk kernel against the FP32 vector peak (algorithmic flops per
+    step x steps per launch / launch time), with the issue-cycle view and the
+    algorithmic bytes beside it."""
+    kind = walk_kind_name(cfg)
+    n_nodes = cfg.get("_nodes", 0)
+    out = {"bound": "alu", "unit": "TFLOP/s", "peak": FP32_PEAK_TFLOPS, "traffic": traffic,
+           "kernel": "walk_kernel<%s, %s, end-of-step exit>" % ("float" if cfg["prec"] == "fp32" else "double",
+                                                                 kind),
+           "flops_per_step": FP32_FLOPS_PER_STEP.get(kind), "steps_per_launch": steps_per_launch,
+           "launch_s": walk_s, "algorithmic_bytes_per_launch": n_nodes * WALK_BYTES_PER_NODE}
+    if cfg["prec"] == "fp32" and kind in FP32_FLOPS_PER_STEP:
+        tf = steps_per_launch * FP32_FLOPS_PER_STEP[kind] / walk_s / 1e12
+        out.update(achieved=tf, frac=tf / FP32_PEAK_TFLOPS, frac_of_unpacked_78_6=tf / (FP32_PEAK_TFLOPS / 2))
+        cyc = CYCLES_PER_WAVE_STEP[kind]
+        g = steps_per_launch / 64 * cyc / walk_s / 1e9
+        out["issue_model"] = {"cycles_per_wave_step": round(cyc, 2), "achieved_G_cycles_per_s": g,
+                              "peak_G_cycles_per_s": ISSUE_PEAK_G, "frac": g / ISSUE_PEAK_G}
+    else:
+        out.update(achieved=None, frac=None)
+    return out
+
+
+def timed_estimate(ctx, dens, B, nodes, paths, dt, seed, prec, exit_test="step", out=None):
+    """One estimate call timed with HIP events on torch's current stream
+    (the stream its kernels run on); returns (result, ms)."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    o = sdd.sdd_interface_estimate(ctx, dens, B, nodes, paths, dt, seed, prec, exit_test=exit_test, out=out)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return o, a.elapsed_time(b)
+
+
+def ring_leg(ctx, oracle_paths: int, want_fp64: bool = True):
+    """The ring workload (1521 nodes x 1e4 paths, dt = 1e-5): float walk rate
+    and roofline, the double walk on the same paths (equal standard error),
+    and its 64-node double-oracle subset node by node (oracle_paths paths)."""
+    import numpy as np
+
+    import paper_1310_3435_amd as sdd
+    import workloads
+    cfg = workloads.cfg_ring_fp32()
+    dens, L = cfg["density"], cfg["layout"]
+    B = sdd.Bmap(cfg["bmap"], ctx, dens)
+    nodes = sdd.sdd_layout_nodes(ctx, L, cfg["k"], "uniform", dens)
+    n = int(nodes.shape[0])
+    cfg["_nodes"] = n
+    est, _ = timed_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp32")
+    ms = []
+    for _ in range(3):
+        est, t = timed_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp32", out=est)
+        ms.append(t)
+    st = sdd.walk_stats(est["stats"])
+    walk_ms = float(np.median(ms))
+    mean32, se32 = est["mean"].cpu().numpy(), est["se"].cpu().numpy()
+    out = {"workload": cfg["name"], "nodes": n, "paths_per_node": cfg["paths"], "dt": cfg["dt"],
+           "walk_ms": walk_ms, "walk_steps_per_s": st["steps"] / (walk_ms / 1e3),
+           "interface_nodes_per_s": n / (walk_ms / 1e3), "median_se": float(np.median(se32)),
+           "t_stoc_ms_device": st["t_stoc_ms"],
+           "roofline": roofline(cfg, st["steps"], walk_ms / 1e3, traffic_from_profile(cfg["name"]))}
+    if want_fp64:
+        e64, _ = timed_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp64")
+        e64, ms64 = timed_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp64", out=e64)
+        st64 = sdd.walk_stats(e64["stats"])
+        d = np.abs(e64["mean"].cpu().numpy() - mean32)
+        z = d / np.maximum(e64["se"].cpu().numpy(), 1e-300)
+        q = lambda a: {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)), "max": float(a.max())}
+        out["fp64_walk"] = {"walk_ms": ms64, "walk_steps_per_s": st64["steps"] / (ms64 / 1e3),
+                            "median_se": float(np.median(e64["se"].cpu().numpy())),
+                            "fp32_speedup_at_equal_se": ms64 / walk_ms,
+                            "node_diff_fp32_vs_fp64": q(d), "node_diff_over_se": q(z)}
+    if oracle_paths > 0:
+        import oracle
+        idx = np.arange(64) * (n // 64)
+        g, _ = timed_estimate(ctx, dens, B, nodes, oracle_paths, cfg["dt"], cfg["seed"], "fp32")
+        gm = g["mean"].cpu().numpy()[idx]
+        t0 = time.perf_counter()
+        r = oracle.interface_estimate(dens, cfg["bmap"], nodes.cpu().numpy()[idx], oracle_paths, cfg["dt"],
+                                      cfg["seed"], "fp64", node_ids=idx, nthreads=host_threads())
+        el = time.perf_counter() - t0
+        z = np.abs(gm - r["mean"]) / r["se"]
+        out["oracle_subset_64"] = {"nodes": "list indices i*%d, i = 0..63" % (n // 64), "paths_per_node": oracle_paths,
+                                   "oracle_s": el, "abs_diff_over_se_max": float(z.max()),
+                                   "abs_diff_over_se_p50": float(np.median(z)),
+                                   "max_abs_diff": float(np.abs(gm - r["mean"]).max()),
+                                   "all_within_3_se": bool(np.all(z <= 3.0))}
+    out["_keep"] = (cfg, B, nodes, walk_ms, st["steps"], mean32)
+    return out
+
+
+def expo_legs(ctx, paths: int):
+    """Exponential time stepping (mean step dt) against the bridge and the
+    end-of-step test at the same dt on the closed-form workload: error
+    against the closed form, steps per path and time."""
+    rows = []
+    for dt in (1e-3, 1e-4):
+        for et in ("expo", "bridge", "step"):
+            r = sin2_estimate(ctx, paths, dt, "fp32", et)
+            r.pop("_mean")
+            rows.append(r)
+    return {"workload": f"sin2_1d_closed_form, 64 nodes x {paths} paths, float walk", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="ring_fp32_4x4x65")
+    ap.add_argument("--workload", default="annulus_fp32_8x8x129")
     ap.add_argument("--prec", default=None, help="override the workload's walk precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-nodes", type=int, default=64)
+    ap.add_argument("--cpu-sample-nodes", type=int, default=8)
+    ap.add_argument("--no-ring", action="store_true", help="skip the ring workload leg")
+    ap.add_argument("--ring-oracle-paths", type=int, default=2000,
+                    help="paths per node of the ring workload's 64-node oracle subset (0: skip)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision comparison walk")
-    ap.add_argument("--serve-requests", type=int, default=48, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="arrival rate / measured capacity")
-    ap.add_argument("--serve-burst", type=int, default=16, help="requests of the capacity burst")
+    ap.add_argument("--serve-burst", type=int, default=32, help="requests of the capacity burst")
     ap.add_argument("--serve-sweep", default="", metavar="LOADS",
                     help="only run the serving stream at each load in LOADS (e.g. 0.5,0.8,1.0), one line each")
     ap.add_argument("--serve-launch-paths", type=int, default=0,
                     help="paths per serving walk launch (0: the server's default)")
-    ap.add_argument("--serve-bridge-dt", type=float, default=0.0,
-                    help="> 0: serving requests use the bridge exit test at this time step")
+    ap.add_argument("--serve-bridge-dt", type=float, default=1e-3,
+                    help="> 0: serving requests use the bridge exit test at this time step (0: end of step, 1e-4)")
     ap.add_argument("--bias-sweep", action="store_true",
                     help="only run the float/double dt sweep of the closed-form workload")
     ap.add_argument("--sweep-paths", type=int, default=1000000)
     ap.add_argument("--sweep-dts", default="1e-3,1e-4,1e-5,1e-6")
-    ap.add_argument("--sweep-exit", default="step,bridge", help="exit tests of the sweep")
+    ap.add_argument("--sweep-exit", default="step,bridge,expo", help="exit tests of the sweep")
     ap.add_argument("--no-quality", action="store_true", help="skip the mesh-quality study")
     ap.add_argument("--bridge-paths", type=int, default=1000000,
                     help="paths per node of the equal-bias comparison (0: skip the bridge legs)")
+    ap.add_argument("--expo-paths", type=int, default=200000,
+                    help="paths per node of the exponential-stepping legs (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (counter calibration)")
     args = ap.parse_args()
@@ -514,9 +658,11 @@ def main():
     B = sdd.Bmap(cfg["bmap"], ctx, dens)
     nodes = sdd.sdd_layout_nodes(ctx, L, cfg["k"], cfg.get("placement", "uniform"), dens)
     n = nodes.shape[0]
+    cfg["_nodes"] = n
     est = None
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
+    interp = cfg.get("interp", "linear")
 
     def step(i=None):
         nonlocal est
@@ -526,9 +672,11 @@ def main():
                                          out=est)
         if i is not None:
             ev[i][1].record(stream)
-        vert, horiz = sdd.sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"))
+        vert, horiz = sdd.sdd_fill_interfaces(ctx, L, cfg["k"], B, nodes, est["mean"], interp)
         return sdd.sdd_subdomain_solve(ctx, dens, B, L, vert, horiz)
 
+    print(f"[bench] {cfg['name']}: {n} nodes x {cfg['paths']} paths, {args.warmup} warmup + {args.steps} timed passes",
+          file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -538,8 +686,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    stats = est["stats"].cpu().numpy()
-    steps_per_pass = int(stats[0])
+    st = sdd.walk_stats(est["stats"])
+    steps_per_pass = int(st["steps"])
     walk_ms = [a.elapsed_time(b) for a, b in ev]
     walk_avg_s = float(np.mean(walk_ms)) / 1e3
     se = est["se"].cpu().numpy()
@@ -549,12 +697,6 @@ def main():
 
     total_steps = steps_per_pass * args.steps
     value = total_steps / elapsed
-    kind = dens["terms"][0]["kind"] if len(dens["terms"]) == 1 else None
-    per_step = CYCLES_PER_WAVE_STEP.get(kind) if cfg["prec"] == "fp32" else None
-    # G SIMD-cycles/s the algorithm's instructions occupy at the measured rate
-    achieved = steps_per_pass / 64 * per_step / walk_avg_s / 1e9 if per_step else None
-    tflops = (steps_per_pass * FP32_FLOPS_PER_STEP[kind] / walk_avg_s / 1e12
-              if cfg["prec"] == "fp32" and kind in FP32_FLOPS_PER_STEP else None)
     line = {
         "metric": "walk steps/s + interface nodes/s at fixed std error; serve p50/p99 latency",
         "value": value,
@@ -569,67 +711,46 @@ def main():
         "dtype": "f32" if cfg["prec"] == "fp32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": cfg["name"], "nodes": n, "paths_per_node": cfg["paths"], "dt": cfg["dt"],
+            "workload": cfg["name"], "nodes": int(n), "paths_per_node": cfg["paths"], "dt": cfg["dt"],
             "layout": f"{L['nx']}x{L['ny']} nodes, {L['sx']}x{L['sy']} subdomains",
-            "walk_precision": cfg["prec"] + " steps, f64 exit projection and sums",
+            "walk_precision": cfg["prec"] + " steps, f64 exit projection, exact node sums",
             "parallelism": "single GPU",
         },
         "interface_nodes_per_s": n * args.steps / elapsed,
         "median_se": float(np.median(se)),
         "walk_steps_per_pass": steps_per_pass,
         "walk_ms": float(np.mean(walk_ms)),
+        "stage_ms": {"t_stoc_device_clock": st["t_stoc_ms"],
+                     "t_fill_plus_sub": elapsed / args.steps * 1e3 - float(np.mean(walk_ms))},
         "fd_sweeps_max": int(sweeps.max()),
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": ISSUE_PEAK_G,
-            "unit": "G SIMD issue-cycles/s",
-            "frac": achieved / ISSUE_PEAK_G if achieved else None,
-            "traffic": traffic_from_profile(args.workload),
-            "kernel": "walk_kernel<%s, %s, end-of-step exit%s>" % (
-                "float" if cfg["prec"] == "fp32" else "double", kind,
-                ", pipelined Philox" if cfg["prec"] == "fp32" and cfg["dt"] < 2e-5 and kind in (None, "sech2", "sin2")
-                else ""),
-            "cycles_per_wave_step": round(per_step, 2) if per_step else None,
-            "fp32_tflops": tflops,
-            "fp32_frac_of_157_3": tflops / FP32_PEAK_TFLOPS if tflops else None,
-            "fp32_frac_of_78_6_unpacked": tflops / (FP32_PEAK_TFLOPS / 2) if tflops else None,
-        },
+        "roofline": roofline(cfg, steps_per_pass, walk_avg_s, traffic_from_profile(args.workload)),
     }
-    if not args.no_fp64 and cfg["prec"] == "fp32":
-        # the same workload with the double-precision walk: same paths, same
-        # uniforms, hence the same standard error
-        e64 = sdd.sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp64")
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        e64 = sdd.sdd_interface_estimate(ctx, dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], "fp64", out=e64)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms64 = a.elapsed_time(b)
-        st64 = int(e64["stats"].cpu().numpy()[0])
-        se64 = float(np.median(e64["se"].cpu().numpy()))
-        # per node: the float walk's estimate against the double walk's (same paths)
-        d = np.abs(e64["mean"].cpu().numpy() - est["mean"].cpu().numpy())
-        z = d / np.maximum(e64["se"].cpu().numpy(), 1e-300)
-        q = lambda a: {"p50": float(np.percentile(a, 50)), "p99": float(np.percentile(a, 99)),
-                       "max": float(a.max())}
-        line["fp64_walk"] = {"walk_ms": ms64, "walk_steps_per_s": st64 / (ms64 / 1e3), "median_se": se64,
-                             "fp32_speedup_at_equal_se": ms64 / float(np.mean(walk_ms)),
-                             "max_node_diff_fp32_vs_fp64": float(d.max()),
-                             "node_diff_fp32_vs_fp64": q(d), "node_diff_over_se": q(z),
-                             "nodes": int(d.shape[0])}
+    print(f"[bench] timed: {value:.3e} walk steps/s, {line['ms_per_step']:.1f} ms/pass", file=sys.stderr, flush=True)
+    gpu_mean = est["mean"].cpu().numpy()
+    ring = None
+    if not args.no_ring:
+        print("[bench] ring workload leg", file=sys.stderr, flush=True)
+        ring = ring_leg(ctx, args.ring_oracle_paths, not args.no_fp64)
+        line["ring"] = {k: v for k, v in ring.items() if not k.startswith("_")}
     if not args.no_quality:
+        print("[bench] quality studies", file=sys.stderr, flush=True)
         line["quality"] = quality_study(ctx, cfg, B, nodes, est["mean"], sol["mesh"])
         line["paper_example"] = paper_study(ctx)
-    if args.bridge_paths > 0:
-        line["bridge"] = bridge_legs(ctx, cfg, B, nodes, float(np.mean(walk_ms)), steps_per_pass,
-                                     est["mean"].cpu().numpy(), args.bridge_paths)
+    if args.bridge_paths > 0 and ring is not None:
+        print("[bench] bridge legs", file=sys.stderr, flush=True)
+        rc, rB, rnodes, rms, rsteps, rmean = ring["_keep"]
+        line["bridge"] = bridge_legs(ctx, rc, rB, rnodes, rms, rsteps, rmean, args.bridge_paths)
+    if args.expo_paths > 0:
+        print("[bench] exponential stepping legs", file=sys.stderr, flush=True)
+        line["expo"] = expo_legs(ctx, args.expo_paths)
     if args.serve_requests > 0:
+        print(f"[bench] serving stream of {args.serve_requests} requests", file=sys.stderr, flush=True)
         line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst,
                                      bridge_dt=args.serve_bridge_dt, launch_paths=args.serve_launch_paths)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes, steps_per_pass)
+        print("[bench] oracle baseline on the host", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes, steps_per_pass,
+                                            gpu_mean=gpu_mean)
     print(json.dumps(line), flush=True)
 
 

@@ -31,8 +31,8 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls enqueue work and return after host-side validation; outputs are
  *     valid once the stream has been synchronised.
- *   - Return values: SDD_OK (0); negative values are errors; no exception
- *     crosses the ABI.  Argument errors (SDD_EINVAL, SDD_ENOSPC) are found
+ *   - Return values: SDD_OK (0); positive values are warnings (the work was
+ *     done); negative values are errors; no exception crosses the ABI.  Argument errors (SDD_EINVAL, SDD_ENOSPC) are found
  *     before anything is enqueued; SDD_EDEVICE reports a failed HIP call,
  *     after which the outputs are undefined.  sdd_status_string() names
  *     them.  A context is not thread-safe; use one per host thread.
@@ -53,6 +53,7 @@ extern "C" {
 
 typedef enum {
     SDD_OK = 0,
+    SDD_WARN_CAPPED = 1,   /* done, but some paths stopped at the step cap (sdd_walk_status, sdd_result) */
     SDD_EINVAL = -1,       /* an argument is out of range or inconsistent */
     SDD_ENOSPC = -2,       /* the workspace is smaller than required */
     SDD_EDEVICE = -3,      /* a HIP runtime call failed */
@@ -68,8 +69,11 @@ typedef enum { SDD_FP64 = 0, SDD_FP32 = 1 } sdd_precision;
  * ends are both inside exits with the probability that the Brownian bridge
  * between them left the square (Sec. 2.2 notes that this conditional
  * probability greatly reduces the error of plain stepping near the
- * boundary). */
-typedef enum { SDD_EXIT_END_OF_STEP = 0, SDD_EXIT_BRIDGE = 1 } sdd_exit_test;
+ * boundary).  EXPONENTIAL: exponential time stepping (Sec. 2.2): every step
+ * has an exponentially distributed length with mean dt (rate lambda =
+ * 1/dt), and the boundary test is both the end-of-step check and the
+ * conditional crossing probability of the step, as for BRIDGE. */
+typedef enum { SDD_EXIT_END_OF_STEP = 0, SDD_EXIT_BRIDGE = 1, SDD_EXIT_EXPONENTIAL = 2 } sdd_exit_test;
 
 /* Density terms; w = base + sum_t amp_t f_t with amp_t >= 0 and base > 0,
  * so w >= base > 0 as eq. (5) requires.  With d = (xi - cx, eta - cy) and
@@ -122,9 +126,12 @@ typedef struct {
 } sdd_layout;
 
 /* Walk totals: sum of exit step counts (the exiting step included), paths
- * walked, paths stopped by the step cap. */
+ * walked, paths stopped by the step cap, and T_stoc (Sec. 5, Tables 5-8):
+ * the device time in ms from the start of the call's first kernel to the
+ * end of its finalize, read from the device wall clock. */
 typedef struct {
     int64_t steps, paths, capped;
+    double t_stoc_ms;
 } sdd_walk_stats;
 
 /* One path's exit (parity mode): exit point, step count, side (0: xi=0,
@@ -168,8 +175,8 @@ void sdd_destroy(sdd_ctx* ctx);
  * first crossing of that step's segment with the boundary, computed in
  * double in both modes, and its value is the boundary map there.  A path
  * still inside after ceil(t_max/dt) steps, rounded up to a multiple of 3
- * (whole Philox blocks), is capped: it takes the value at the nearest boundary point and is counted
- * in stats->capped.
+ * (whole Philox blocks), is capped: it takes the value at the nearest
+ * boundary point and is counted in stats->capped.
  *
  * exit_test SDD_EXIT_BRIDGE adds, after a step P -> Q with both ends inside,
  * the bridge test: each coordinate of the Brownian bridge from P to Q is an
@@ -182,16 +189,32 @@ void sdd_destroy(sdd_ctx* ctx);
  * A bridged exit leaves through the nearer wall of the axis with the larger
  * probability (xi on ties), at Q moved onto that wall; these decisions are
  * taken in the walk precision.  Its bias in the exit point is O(dt) where
- * the end-of-step test's is O(sqrt dt).  Per-node sums are accumulated in double with
- * compensation, in a fixed order, so results do not depend on scheduling.
- * The workspace holds every path's last step (16 bytes in float, 32 in
- * double) and step count (4 bytes): n_nodes * N must stay below
- * 2^32 - 2^24.
+ * the end-of-step test's is O(sqrt dt).
+ *
+ * exit_test SDD_EXIT_EXPONENTIAL (exponential time stepping): step 3m + j
+ * has length tau = -ln(u) dt, u from word j of the block of counter
+ * (m, p, g, 2) formed as for the bridge, so tau is exponential with mean dt;
+ * X <- X + (grad w / w)(X) tau + sqrt(2 tau) Z, the exact law of the
+ * diffusion with the drift frozen over the step; and the bridge test above
+ * with tau in place of dt, which given tau is the exact crossing
+ * probability of that process.  The step cap counts steps as above
+ * (ceil(t_max/dt), i.e. t_max in expectation).
+ *
+ * Node sums are exact: each path's x, y, x^2, y^2 is rounded to a multiple
+ * of 2^-F (2^-60 times a power of two bounding the boundary map's image,
+ * from its parameters or, for a TABLE map, its table) and added into
+ * 64-bit integer limbs, so the sums are independent of the order in which
+ * paths finish and the results are bitwise reproducible.  The workspace
+ * holds these sums (96 bytes per node) and a 256-byte header; the walk
+ * keeps each finished path only in on-chip memory until its exit is
+ * processed.
  *
  *   w, bmap      host structs (bmap->table, if any, is device memory)
- *   nodes        device [n_nodes][2], every point strictly inside (0,1)^2
- *   paths_per_node  N >= 1; paths path_begin .. path_begin+N-1 are walked
- *   dt           0 < dt < 1, and ceil(t_max/dt) < 2^28 - 3
+ *   nodes        device [n_nodes][2]; 1 <= n_nodes < 2^32
+ *   paths_per_node  1 <= N < 2^32; paths path_begin .. path_begin+N-1 are
+ *                walked (path_begin + N <= 2^32)
+ *   dt           0 < dt < 1 (the mean step for SDD_EXIT_EXPONENTIAL), and
+ *                ceil(t_max/dt) < 2^28 - 3
  *   t_max        step cap in time units; <= 0 selects 8
  *   exit_test    sdd_exit_test
  *   mean         device [n][2]   sum / N
@@ -203,7 +226,9 @@ void sdd_destroy(sdd_ctx* ctx);
  *   workspace    device, >= sdd_workspace_bytes(n_nodes, N, prec) bytes
  * Errors: SDD_EINVAL (bad argument), SDD_ENOSPC, SDD_EDEVICE.  Node
  * positions live on the device and are not read by the host: a node on or
- * outside the boundary walks no path and gets NaN mean, SE and sums. */
+ * outside the boundary walks no path and gets NaN mean, SE and sums (and
+ * per-path records with NaN exit, 0 steps, side -1).  Capped paths are a
+ * device-side condition: read stats and pass it to sdd_walk_status. */
 size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec);
 
 sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap,
@@ -212,6 +237,10 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
                                   int32_t exit_test, double* mean, double* se, double* sums,
                                   sdd_walk_stats* stats, sdd_path_record* per_path, void* workspace,
                                   size_t ws_bytes, void* stream);
+
+/* SDD_WARN_CAPPED if the host copy of a walk's stats counts capped paths,
+ * SDD_OK otherwise; SDD_EINVAL for NULL. */
+sdd_status sdd_walk_status(const sdd_walk_stats* stats);
 
 /* ----------------------------------------------------------- interfaces ---
  * Interface points of a layout (Sec. 2.1, Fig. 1): the (sx-1)(sy-1)
@@ -295,7 +324,11 @@ sdd_status sdd_fill_interfaces_counts(sdd_ctx* ctx, const sdd_layout* L, int32_t
  * interface lines hold vert/horiz, every subdomain interior its solution.
  * sweeps (device [sx*sy] int32 or NULL) and resid (device [sx*sy] double or
  * NULL) report, per subdomain b*sx + a, the sweeps taken and the last
- * largest change (the larger of the two components). */
+ * largest change (the larger of the two components).
+ * The solve is double only, on purpose: it is a few percent of a pass
+ * (T_sub, Sec. 5), its subdomains stay in LDS in double, and a float
+ * iteration would stall near 1e-7 of the map's scale, far above the 1e-13
+ * the stopping rule reaches and to which the result is checked. */
 size_t sdd_subdomain_workspace_bytes(const sdd_layout* L);
 
 sdd_status sdd_subdomain_solve(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const sdd_layout* L,
@@ -385,27 +418,29 @@ sdd_status sdd_smooth_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t span
  * others run are admitted as slots and device memory free up, and every
  * walk launch mixes blocks of paths from all admitted requests.
  *
- * Paths are walked in blocks of 1024 per node.  With se_target > 0 the
+ * Paths are scheduled in blocks of 1024 per node.  With se_target > 0 the
  * first block is a pilot; the request then runs
  * N = max(1024, ceil((s / se_target)^2)) paths per node, rounded up to a
  * multiple of 1024, where s is the largest sample standard deviation of x
  * or y over its nodes (the paper notes the mean's additivity makes such a
  * stopping rule compatible with the method, Sec. 6).  With se_target <= 0
- * paths_per_node is used, rounded up to a multiple of 1024.  Block b of a
- * request is always reduced before block b+1, and a path's random numbers
- * depend only on (seed, node, path, step), so a request's result is
- * bitwise the same alone or in any mix.
+ * paths_per_node (<= 2^30) is used, rounded up to a multiple of 1024.  The
+ * node sums are exact and a path's random numbers depend only on (seed,
+ * node, path, step), so a request's result is bitwise the same alone or in
+ * any mix.
  *
- * Requests walk in float (compensated double sums, double exit
- * projection) with the exit test of sdd_interface_estimate that
- * exit_test names; the density must be a sum of up to four GAUSS terms; the
- * boundary map IDENTITY, AFFINE or ANNULUS.  A request's device footprint
+ * Requests walk in float (exact node sums, double exit projection) with
+ * the exit test of sdd_interface_estimate that exit_test names
+ * (END_OF_STEP or BRIDGE); the density must be a sum of up to four GAUSS
+ * terms; the boundary map IDENTITY, AFFINE or ANNULUS.  A request walks
+ * exactly the paths an sdd_interface_estimate call (SDD_FP32, path_begin 0,
+ * the request's nodes, N = its paths per node) walks, and its node
+ * estimates are bitwise those of that call.  A request's device footprint
  * (nodes, sums, interface lines, mesh, subdomain workspace) comes from an
  * arena of hbm_budget_bytes allocated once at creation; a request is
  * admitted first come, first served when a slot and enough arena are free.
- * The server also holds two path-record buffers of launch_paths x 20 bytes
- * and pinned host staging of max_slots x (max_nodes x 80 + max_points x 16)
- * bytes.  A scheduler thread owns the device work; every call below is
+ * The server also holds pinned host staging of
+ * max_slots x (max_nodes x 112 + max_points x 16) bytes.  A scheduler thread owns the device work; every call below is
  * thread-safe.  Times are seconds on the server's steady clock. */
 typedef struct {
     sdd_density w;
@@ -423,11 +458,17 @@ typedef struct {
 } sdd_request;
 
 typedef struct {
-    int32_t status; /* SDD_OK, SDD_ECANCELED or an error */
+    int32_t status; /* SDD_OK, SDD_WARN_CAPPED (done; some paths capped), SDD_ECANCELED or an error */
     int32_t pad;
-    int64_t n_nodes, paths_per_node, steps;
+    int64_t n_nodes, paths_per_node, steps, capped;
     double max_se;  /* largest node standard error over both components */
     double t_submit, t_admit, t_done; /* t_done: the mesh is in the caller's buffer */
+    /* stage times in ms (Sec. 5: T_stoc, T_sub): waiting for admission
+     * (host clock); the request's walks, from the start of the first walk
+     * launch holding one of its blocks to the end of the last (device
+     * events; other requests share those launches); finalize + interface
+     * fill; subdomain solves */
+    double t_queue_ms, t_stoc_ms, t_fill_ms, t_sub_ms;
 } sdd_result;
 
 typedef struct sdd_server sdd_server;

@@ -102,6 +102,7 @@ def lib():
         L.sddref_bridge_uniforms.argtypes = [C.c_int64, P, P]
         L.sddref_bridge_exit_prob.argtypes = [C.c_double] * 5 + [P]
         L.sddref_bridge_exit_prob.restype = C.c_double
+        L.sddref_expo_steps.argtypes = [C.c_int64, P, C.c_double, P]
         L.sddref_interface_estimate.argtypes = [
             C.POINTER(RefDensity), C.POINTER(RefBmap), P, P, C.c_int64, C.c_int64, C.c_int64,
             C.c_double, C.c_uint64, C.c_int, C.c_double, C.c_int, C.c_int, P, P, P, P, P, C.c_int]
@@ -233,19 +234,35 @@ def bridge_exit_prob(p, q, dt: float):
     return prob, side.value
 
 
+def expo_steps(words: np.ndarray, dt: float) -> np.ndarray:
+    """Exponential step lengths tau = -ln(u) dt from words of the
+    counter-word-3 = 2 blocks (u formed as for the bridge test)."""
+    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1)
+    tau = np.empty(words.shape[0], dtype=np.float64)
+    lib().sddref_expo_steps(words.shape[0], _ptr(words), float(dt), _ptr(tau))
+    return tau
+
+
 # ------------------------------------------------------------------ estimate
+
+_EXIT = {"step": 0, "bridge": 1, "expo": 2}
+
 
 def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: float, seed: int,
                        prec: str = "fp64", t_max: float = 8.0, node_ids=None, path_begin: int = 0,
                        per_path: bool = False, proj_mode: int = 0, nthreads: int = 0,
-                       bridge: bool = False, allow_off: bool = False) -> dict:
+                       bridge: bool = False, allow_off: bool = False, exit_test: str = None) -> dict:
     """Monte Carlo estimate of (x, y) at every node (eq. (7a), Sec. 2.2).
 
-    bridge=True adds the Brownian-bridge exit test after every step (the
-    conditional exit probability of Sec. 2.2).
+    exit_test: "step" (end of step), "bridge" (plus the Brownian-bridge
+    test: the conditional exit probability of Sec. 2.2) or "expo"
+    (exponential time stepping with mean step dt, Sec. 2.2).  bridge=True is
+    exit_test="bridge".
 
     Returns dict(mean[n,2], se[n,2], sums[n,4], steps, paths, capped[, per_path]).
     """
+    if exit_test is None:
+        exit_test = "bridge" if bridge else "step"
     B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, density)
     D = make_density(density)
     nodes = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 2)
@@ -255,7 +272,7 @@ def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: f
         inside = (nodes[:, 0] > 0) & (nodes[:, 0] < 1) & (nodes[:, 1] > 0) & (nodes[:, 1] < 1)
         idx = np.flatnonzero(inside) if node_ids is None else np.asarray(node_ids)[inside]
         sub = interface_estimate(density, B, nodes[inside], paths, dt, seed, prec, t_max, idx, path_begin,
-                                 per_path, proj_mode, nthreads, bridge)
+                                 per_path, proj_mode, nthreads, exit_test=exit_test)
         out = dict(sub)
         for key, width in (("mean", 2), ("se", 2), ("sums", 4)):
             full = np.full((nodes.shape[0], width), np.nan)
@@ -272,7 +289,7 @@ def interface_estimate(density: dict, bmap, nodes: np.ndarray, paths: int, dt: f
     rec = np.zeros((n, paths), dtype=PATH_RECORD) if per_path else None
     rc = lib().sddref_interface_estimate(
         C.byref(D), C.byref(B.s), _ptr(nodes), _ptr(ids), n, int(paths), int(path_begin), float(dt),
-        C.c_uint64(int(seed)), _PREC[prec], float(t_max), int(proj_mode), int(bool(bridge)), _ptr(mean), _ptr(se),
+        C.c_uint64(int(seed)), _PREC[prec], float(t_max), int(proj_mode), _EXIT[exit_test], _ptr(mean), _ptr(se),
         _ptr(sums), _ptr(stats), _ptr(rec), int(nthreads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
@@ -703,7 +720,7 @@ def probabilistic_mesh(cfg: dict, nthreads: int = 0) -> dict:
     nx, ny = cfg["layout"]["nx"], cfg["layout"]["ny"]
     nodes = grid_nodes(nx, ny)
     est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
-                             nthreads=nthreads, bridge=cfg.get("exit_test", "step") == "bridge")
+                             nthreads=nthreads, exit_test=cfg.get("exit_test", "step"))
     mesh = assemble_mesh(B, nx, ny, est["mean"])
     pm = cfg.get("pm")
     if pm:
@@ -724,7 +741,7 @@ def pipeline(cfg: dict, nthreads: int = 0) -> dict:
         nodes = layout_nodes(L, cfg["k"], cfg.get("placement", "uniform"), dens)
     est = interface_estimate(dens, B, nodes, cfg["paths"], cfg["dt"], cfg["seed"], cfg.get("prec", "fp64"),
                              t_max=cfg.get("t_max", 8.0), nthreads=nthreads,
-                             bridge=cfg.get("exit_test", "step") == "bridge", allow_off=True)
+                             exit_test=cfg.get("exit_test", "step"), allow_off=True)
     vert, horiz = fill_interfaces(L, cfg["k"], B, nodes, est["mean"], cfg.get("interp", "linear"), counts=counts)
     if cfg.get("smooth_span", 0) > 0:
         vert, horiz = smooth_interfaces(L, vert, horiz, int(cfg["smooth_span"]))

@@ -33,7 +33,12 @@
  *     Philox blocks); a capped path takes the boundary value at the nearest
  *     boundary point and is counted;
  *   - the Brownian-bridge test of step 3m+j draws word j of the block with
- *     counter (m, p, g, 1).
+ *     counter (m, p, g, 1);
+ *   - exponential time stepping (Sec. 2.2): step 3m+j has the length
+ *     tau = -ln(u) dt, u formed from word j of the block with counter
+ *     (m, p, g, 2) as for the bridge, so that tau is exponential with mean
+ *     dt; the step is Euler-Maruyama with that length and the exit test is
+ *     the end-of-step check plus the bridge test with tau in place of dt.
  */
 #include <math.h>
 #include <stdint.h>
@@ -402,6 +407,16 @@ static void onto_side(int s, double qx, double qy, double* ex, double* ey)
     *ey = (s == 2) ? 0.0 : (s == 3) ? 1.0 : qy;
 }
 
+/* Exponential time stepping: the length of a step from its uniform word,
+ * tau = -ln(u) dt (an exponential variate with mean dt, rate 1/dt). */
+static double expo_tau(uint32_t q, double dt) { return -log(bridge_uniform(q)) * dt; }
+
+/* Exponential step lengths of n words (test access). */
+void sddref_expo_steps(int64_t n, const uint32_t* words, double dt, double* tau)
+{
+    for (int64_t i = 0; i < n; ++i) tau[i] = expo_tau(words[i], dt);
+}
+
 /* ------------------------------------------------------------ one path */
 
 typedef struct {
@@ -415,14 +430,16 @@ typedef struct {
 /* proj_mode 0: value at the projected exit point (the method).
  * proj_mode 1: test mode, the map evaluated at the unprojected overshoot
  *              point X_{k+1} (only meaningful for identity/affine maps).
- * exit_test 1: also apply the Brownian-bridge exit test after each step. */
+ * exit_test 1: also apply the Brownian-bridge exit test after each step.
+ * exit_test 2: exponential time stepping (steps of random length tau, the
+ *              bridge test with tau). */
 static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, double eta0,
                         uint64_t g, uint64_t p, double dt, const uint32_t key[2], int64_t kmax,
-                        int proj_mode, int bridge, path_out* o)
+                        int proj_mode, int exit_test, path_out* o)
 {
-    const double s = sqrt(2.0 * dt);
+    const int bridge = exit_test != 0;
     double X = xi0, Y = eta0;
-    uint32_t r[4] = { 0, 0, 0, 0 }, q[4] = { 0, 0, 0, 0 };
+    uint32_t r[4] = { 0, 0, 0, 0 }, q[4] = { 0, 0, 0, 0 }, e[4] = { 0, 0, 0, 0 };
     int64_t k = 0;
     for (;;) {
         if (k == kmax) {
@@ -438,15 +455,21 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
                 ctr[3] = 1u;
                 sddref_philox4x32_10(ctr, key, q);
             }
+            if (exit_test == 2) {
+                ctr[3] = 2u;
+                sddref_philox4x32_10(ctr, key, e);
+            }
         }
+        const double h = (exit_test == 2) ? expo_tau(e[j], dt) : dt;  /* this step's length */
+        const double s = sqrt(2.0 * h);
         uint32_t ra, rb;
         block_fields(r, j, &ra, &rb);
         double zx, zy, w, gx, gy;
         box_muller64(ra, rb, &zx, &zy);
         density64(d, X, Y, &w, &gx, &gy);
         double bx = gx / w, by = gy / w;
-        double Xn = fma(s, zx, fma(bx, dt, X));
-        double Yn = fma(s, zy, fma(by, dt, Y));
+        double Xn = fma(s, zx, fma(bx, h, X));
+        double Yn = fma(s, zy, fma(by, h, Y));
         ++k;
         if (Xn <= 0.0 || Xn >= 1.0 || Yn <= 0.0 || Yn >= 1.0) {
             if (proj_mode == 1) {
@@ -458,7 +481,7 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
             break;
         }
         if (bridge) {
-            int sb = bridge_exit64(X, Y, Xn, Yn, dt, bridge_uniform(q[j]));
+            int sb = bridge_exit64(X, Y, Xn, Yn, h, bridge_uniform(q[j]));
             if (sb >= 0) {
                 onto_side(sb, Xn, Yn, &o->exi, &o->eeta);
                 o->side = sb;
@@ -474,12 +497,11 @@ static void walk_path64(const ref_density* d, const ref_bmap* b, double xi0, dou
 
 static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, double eta0,
                         uint64_t g, uint64_t p, double dt, const uint32_t key[2], int64_t kmax,
-                        int proj_mode, int bridge, path_out* o)
+                        int proj_mode, int exit_test, path_out* o)
 {
-    const float s = (float)sqrt(2.0 * dt);
-    const float dtf = (float)dt;
+    const int bridge = exit_test != 0;
     float X = (float)xi0, Y = (float)eta0;
-    uint32_t r[4] = { 0, 0, 0, 0 }, q[4] = { 0, 0, 0, 0 };
+    uint32_t r[4] = { 0, 0, 0, 0 }, q[4] = { 0, 0, 0, 0 }, e[4] = { 0, 0, 0, 0 };
     int64_t k = 0;
     for (;;) {
         if (k == kmax) {
@@ -495,15 +517,22 @@ static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, dou
                 ctr[3] = 1u;
                 sddref_philox4x32_10(ctr, key, q);
             }
+            if (exit_test == 2) {
+                ctr[3] = 2u;
+                sddref_philox4x32_10(ctr, key, e);
+            }
         }
+        /* this step's length and noise factor, in float */
+        const float h = (exit_test == 2) ? -logf((float)bridge_uniform(e[j])) * (float)dt : (float)dt;
+        const float s = (exit_test == 2) ? sqrtf(2.0f * h) : (float)sqrt(2.0 * dt);
         uint32_t ra, rb;
         block_fields(r, j, &ra, &rb);
         float zx, zy, w, gx, gy;
         box_muller32(ra, rb, &zx, &zy);
         density32(d, X, Y, &w, &gx, &gy);
         float bx = gx / w, by = gy / w;
-        float Xn = fmaf(s, zx, fmaf(bx, dtf, X));
-        float Yn = fmaf(s, zy, fmaf(by, dtf, Y));
+        float Xn = fmaf(s, zx, fmaf(bx, h, X));
+        float Yn = fmaf(s, zy, fmaf(by, h, Y));
         ++k;
         if (Xn <= 0.0f || Xn >= 1.0f || Yn <= 0.0f || Yn >= 1.0f) {
             if (proj_mode == 1) {
@@ -515,7 +544,7 @@ static void walk_path32(const ref_density* d, const ref_bmap* b, double xi0, dou
             break;
         }
         if (bridge) {
-            int sb = bridge_exit32(X, Y, Xn, Yn, dtf, (float)bridge_uniform(q[j]));
+            int sb = bridge_exit32(X, Y, Xn, Yn, h, (float)bridge_uniform(q[j]));
             if (sb >= 0) {
                 onto_side(sb, (double)Xn, (double)Yn, &o->exi, &o->eeta);
                 o->side = sb;
@@ -550,7 +579,8 @@ static double nsum_get(const nsum* a) { return a->s + a->c; }
  * paths, path_begin paths path_begin .. path_begin+paths-1 are walked
  * mean[n][2], se[n][2]  outputs; sums[n][4] (optional) = sum x, sum y,
  *                   sum x^2, sum y^2 before division
- * exit_test         0: end-of-step test only; 1: also the Brownian-bridge test
+ * exit_test         0: end-of-step test only; 1: also the Brownian-bridge test;
+ *                   2: exponential time stepping with mean step dt
  * stats[3]          total steps, total paths, capped paths
  * per_path[n][paths] optional records
  * Returns 0, or -1 on invalid arguments.
@@ -562,7 +592,7 @@ int sddref_interface_estimate(const ref_density* d, const ref_bmap* b, const dou
                               ref_path_record* per_path, int nthreads)
 {
     if (n < 1 || paths < 1 || !(dt > 0.0) || !(dt < 1.0) || path_begin < 0) return -1;
-    if (exit_test != 0 && exit_test != 1) return -1;
+    if (exit_test < 0 || exit_test > 2) return -1;
     for (int64_t i = 0; i < n; ++i) {
         double a = nodes[2 * i], c = nodes[2 * i + 1];
         if (!(a > 0.0 && a < 1.0 && c > 0.0 && c < 1.0)) return -1;

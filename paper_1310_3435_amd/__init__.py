@@ -24,8 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libsdd.so")
 
 SDD_FP64, SDD_FP32 = 0, 1
 PREC = {"fp64": SDD_FP64, "fp32": SDD_FP32}
-SDD_EXIT_END_OF_STEP, SDD_EXIT_BRIDGE = 0, 1
-EXIT_TEST = {"step": SDD_EXIT_END_OF_STEP, "bridge": SDD_EXIT_BRIDGE}
+SDD_EXIT_END_OF_STEP, SDD_EXIT_BRIDGE, SDD_EXIT_EXPONENTIAL = 0, 1, 2
+EXIT_TEST = {"step": SDD_EXIT_END_OF_STEP, "bridge": SDD_EXIT_BRIDGE, "expo": SDD_EXIT_EXPONENTIAL}
 TERM = {"gauss": 0, "ring": 1, "sech2": 2, "sin2": 3}
 BMAP = {"identity": 0, "affine": 1, "annulus": 2, "table": 3}
 PLACEMENT = {"uniform": 0, "equidistributed": 1}
@@ -35,6 +35,10 @@ MAX_TERMS = 4
 
 class SddError(RuntimeError):
     pass
+
+
+class SddCappedWarning(UserWarning):
+    """Some paths stopped at the step cap (SDD_WARN_CAPPED)."""
 
 
 class sdd_density_term(C.Structure):
@@ -57,7 +61,7 @@ class sdd_layout(C.Structure):
 
 
 class sdd_walk_stats(C.Structure):
-    _fields_ = [("steps", C.c_int64), ("paths", C.c_int64), ("capped", C.c_int64)]
+    _fields_ = [("steps", C.c_int64), ("paths", C.c_int64), ("capped", C.c_int64), ("t_stoc_ms", C.c_double)]
 
 
 class sdd_request(C.Structure):
@@ -69,10 +73,12 @@ class sdd_request(C.Structure):
 
 class sdd_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("pad", C.c_int32), ("n_nodes", C.c_int64), ("paths_per_node", C.c_int64),
-                ("steps", C.c_int64), ("max_se", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double)]
+                ("steps", C.c_int64), ("capped", C.c_int64), ("max_se", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("t_queue_ms", C.c_double),
+                ("t_stoc_ms", C.c_double), ("t_fill_ms", C.c_double), ("t_sub_ms", C.c_double)]
 
 
+SDD_OK, SDD_WARN_CAPPED = 0, 1
 SDD_EINVAL, SDD_EAGAIN, SDD_ECANCELED, SDD_EUNSUPPORTED = -1, -4, -5, -6
 
 PATH_RECORD = np.dtype([("exit_xi", "<f8"), ("exit_eta", "<f8"), ("steps", "<i8"), ("side", "<i4"),
@@ -102,6 +108,8 @@ def lib() -> C.CDLL:
     L.sdd_interface_estimate.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), P, I64, I64, I64, D, U64,
                                          I32, D, I32, P, P, P, P, P, P, SZ, P]
     L.sdd_interface_estimate.restype = C.c_int
+    L.sdd_walk_status.argtypes = [C.POINTER(sdd_walk_stats)]
+    L.sdd_walk_status.restype = C.c_int
     L.sdd_layout_node_count.argtypes = [C.POINTER(sdd_layout), I32]
     L.sdd_layout_node_count.restype = I64
     L.sdd_layout_nodes.argtypes = [P, C.POINTER(sdd_layout), I32, I32, C.POINTER(sdd_density), P, P]
@@ -157,7 +165,7 @@ def lib() -> C.CDLL:
 
 
 EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd_workspace_bytes",
-           "sdd_interface_estimate", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
+           "sdd_interface_estimate", "sdd_walk_status", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
            "sdd_fill_interfaces", "sdd_subdomain_workspace_bytes", "sdd_subdomain_solve", "sdd_server_create",
            "sdd_server_submit", "sdd_server_poll", "sdd_server_wait", "sdd_server_cancel", "sdd_server_clock",
            "sdd_server_destroy", "sdd_quality_workspace_bytes", "sdd_mesh_quality", "sdd_mesh_compare",
@@ -312,13 +320,14 @@ def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_n
                            stream=None, out: Optional[dict] = None, exit_test: str = "step") -> dict:
     """Monte Carlo estimate at every node (device tensors in, device tensors out).
 
-    exit_test: "step" (end-of-step test) or "bridge" (plus the Brownian-bridge
-    test).
+    exit_test: "step" (end-of-step test), "bridge" (plus the Brownian-bridge
+    test) or "expo" (exponential time stepping with mean step dt).
     nodes: device float64 [n, 2].  Returns dict with 'mean' [n,2], and as
-    requested 'se' [n,2], 'sums' [n,4], 'stats' (int64 [3]: steps, paths,
-    capped) and 'per_path' (uint8 [n, N, 32] records).  Results are valid
-    after the stream synchronises.  Pass ``out`` (a previous result dict) to
-    reuse its buffers.
+    requested 'se' [n,2], 'sums' [n,4], 'stats' (int64 [4]: steps, paths,
+    capped, and the walk time in ms as the bits of a float64; see
+    walk_stats) and 'per_path' (uint8 [n, N, 32] records).  Results are
+    valid after the stream synchronises.  Pass ``out`` (a previous result
+    dict) to reuse its buffers: each is checked against this call's shape.
     """
     torch = _torch()
     B = bmap if isinstance(bmap, Bmap) else Bmap(bmap, ctx, density)
@@ -326,18 +335,24 @@ def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_n
     n = int(nodes.shape[0])
     dev = nodes.device
     f64 = dict(dtype=torch.float64, device=dev)
+    want = {"mean": ((n, 2), torch.float64, True), "se": ((n, 2), torch.float64, want_se),
+            "sums": ((n, 4), torch.float64, want_sums), "stats": ((4,), torch.int64, want_stats),
+            "per_path": ((n, int(paths_per_node), 32), torch.uint8, per_path)}
     o = out if out is not None else {}
-    if "mean" not in o:
-        o["mean"] = torch.empty((n, 2), **f64)
-        if want_se:
-            o["se"] = torch.empty((n, 2), **f64)
-        if want_sums:
-            o["sums"] = torch.empty((n, 4), **f64)
-        if want_stats:
-            o["stats"] = torch.empty(3, dtype=torch.int64, device=dev)
-        if per_path:
-            o["per_path"] = torch.empty((n, int(paths_per_node), 32), dtype=torch.uint8, device=dev)
+    for key, (shape, dtype, on) in want.items():
+        t = o.get(key)
+        if not on:
+            o.pop(key, None)
+            continue
+        if t is not None and (tuple(t.shape) != shape or t.dtype != dtype or t.device != dev
+                              or not t.is_contiguous()):
+            raise SddError(f"out['{key}'] has shape {tuple(t.shape)} {t.dtype} on {t.device}; "
+                           f"this call needs {shape} {dtype} on {dev}")
+        if t is None:
+            o[key] = torch.empty(shape, dtype=dtype, device=dev)
     wsb = sdd_workspace_bytes(n, paths_per_node, prec)
+    if wsb == 0:
+        raise SddError("sdd_interface_estimate: invalid argument (node or path count)")
     ws = ctx.workspace(wsb)
     rc = lib().sdd_interface_estimate(
         ctx.h, C.byref(D), C.byref(B.s), _ptr(nodes), n, int(paths_per_node), int(path_begin), float(dt),
@@ -347,6 +362,19 @@ def sdd_interface_estimate(ctx: Context, density: dict, bmap, nodes, paths_per_n
     _check(rc, "sdd_interface_estimate")
     o["_bmap"] = B
     return o
+
+
+def walk_stats(stats, warn: bool = True) -> dict:
+    """Host view of a walk's device stats (int64 [4]): steps, paths, capped,
+    t_stoc_ms.  Synchronises with the stats' producer (a device-to-host
+    copy).  Warns (SddCappedWarning) when sdd_walk_status reports capped
+    paths."""
+    a = stats.cpu().numpy()
+    s = sdd_walk_stats(int(a[0]), int(a[1]), int(a[2]), float(a[3:4].view(np.float64)[0]))
+    if warn and lib().sdd_walk_status(C.byref(s)) == SDD_WARN_CAPPED:
+        import warnings
+        warnings.warn(f"{s.capped} of {s.paths} paths stopped at the step cap", SddCappedWarning, stacklevel=2)
+    return {"steps": s.steps, "paths": s.paths, "capped": s.capped, "t_stoc_ms": s.t_stoc_ms}
 
 
 def path_records(per_path) -> np.ndarray:
@@ -633,9 +661,12 @@ class Server:
         return rid.value
 
     def _result(self, rc, res, rid):
+        """status 0 (SDD_OK) or 1 (SDD_WARN_CAPPED: done, some paths capped)
+        means the mesh is there; negative values are errors."""
         out = {"status": rc, "n_nodes": res.n_nodes, "paths_per_node": res.paths_per_node, "steps": res.steps,
-               "max_se": res.max_se, "t_submit": res.t_submit, "t_admit": res.t_admit, "t_done": res.t_done,
-               "mesh": self.meshes.pop(rid, None)}
+               "capped": res.capped, "max_se": res.max_se, "t_submit": res.t_submit, "t_admit": res.t_admit,
+               "t_done": res.t_done, "t_queue_ms": res.t_queue_ms, "t_stoc_ms": res.t_stoc_ms,
+               "t_fill_ms": res.t_fill_ms, "t_sub_ms": res.t_sub_ms, "mesh": self.meshes.pop(rid, None)}
         return out
 
     def poll(self, rid: int):

@@ -17,16 +17,14 @@ using namespace sdd;
 
 namespace sdd {
 
-WalkWorkspace walk_workspace(int64_t n_nodes, int64_t paths, int prec)
+WalkWorkspace walk_workspace(int64_t n_nodes)
 {
     WalkWorkspace W;
-    const size_t total = (size_t)n_nodes * (size_t)paths;
-    const size_t real = (prec == SDD_FP32) ? sizeof(float) : sizeof(double);
-    W.pq_off = 0;
-    W.info_off = align_up(W.pq_off + total * 4 * real, 256);
-    W.counter_off = align_up(W.info_off + total * sizeof(uint32_t), 256);
-    W.node_tot_off = align_up(W.counter_off + sizeof(unsigned long long), 256);
-    W.bytes = align_up(W.node_tot_off + (size_t)n_nodes * 2 * sizeof(long long), 256);
+    W.counter_off = 0;
+    W.scale_off = 64;
+    W.clock_off = 128;
+    W.acc_off = 256;
+    W.bytes = align_up(W.acc_off + (size_t)n_nodes * sizeof(NodeAcc), 256);
     return W;
 }
 
@@ -38,6 +36,7 @@ const char* sdd_status_string(int status)
 {
     switch (status) {
     case SDD_OK: return "ok";
+    case SDD_WARN_CAPPED: return "some paths stopped at the step cap";
     case SDD_EINVAL: return "invalid argument";
     case SDD_ENOSPC: return "workspace too small";
     case SDD_EDEVICE: return "HIP runtime error";
@@ -48,7 +47,7 @@ const char* sdd_status_string(int status)
     }
 }
 
-int32_t sdd_version(void) { return 100; }
+int32_t sdd_version(void) { return 200; }
 
 sdd_status sdd_create(int32_t device, sdd_ctx** out)
 {
@@ -63,6 +62,9 @@ sdd_status sdd_create(int32_t device, sdd_ctx** out)
     if (!c) return SDD_EDEVICE;
     c->device = device;
     c->cu_count = prop.multiProcessorCount;
+    int rate = 0;
+    if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) != hipSuccess) rate = 0;
+    c->wall_rate_khz = rate;
     *out = c;
     return SDD_OK;
 }
@@ -71,10 +73,95 @@ void sdd_destroy(sdd_ctx* ctx) { delete ctx; }
 
 size_t sdd_workspace_bytes(int64_t n_nodes, int64_t paths_per_node, int32_t prec)
 {
-    if (n_nodes < 1 || paths_per_node < 1) return 0;
-    if (n_nodes * paths_per_node >= kMaxTickets) return 0;
-    return walk_workspace(n_nodes, paths_per_node, prec).bytes;
+    (void)prec;
+    if (n_nodes < 1 || n_nodes > kMaxNodes || paths_per_node < 1 || paths_per_node > kMaxPathsPerNode) return 0;
+    return walk_workspace(n_nodes).bytes;
 }
+
+namespace {
+
+// Validation shared by sdd_interface_estimate and its allocation-free
+// variant; fills A (without the workspace pointers) and the step cap.
+sdd_status prepare_estimate(const sdd_density* w, const sdd_bmap* bmap, const double* nodes, int64_t n_nodes,
+                            int64_t paths_per_node, int64_t path_begin, double dt, uint64_t seed, int32_t prec,
+                            double t_max, int32_t exit_test, const double* mean, int cu_count, WalkArgs& A)
+{
+    if (!nodes || !mean) return SDD_EINVAL;
+    sdd_status s = check_density(w);
+    if (s != SDD_OK) return s;
+    if ((s = check_bmap(bmap)) != SDD_OK) return s;
+    if (n_nodes < 1 || n_nodes > kMaxNodes) return SDD_EINVAL;
+    if (paths_per_node < 1 || paths_per_node > kMaxPathsPerNode || path_begin < 0) return SDD_EINVAL;
+    if (path_begin + paths_per_node > ((int64_t)1 << 32)) return SDD_EINVAL;
+    if (!(dt > 0.0) || !(dt < 1.0)) return SDD_EINVAL;
+    if (prec != SDD_FP32 && prec != SDD_FP64) return SDD_EINVAL;
+    if (exit_test != SDD_EXIT_END_OF_STEP && exit_test != SDD_EXIT_BRIDGE && exit_test != SDD_EXIT_EXPONENTIAL)
+        return SDD_EINVAL;
+    if (!(t_max > 0.0)) t_max = 8.0;
+    if (!is_finite(t_max)) return SDD_EINVAL;
+    const int32_t kmax = step_cap(t_max, dt);
+    if (kmax < 0) return SDD_EINVAL;
+
+    memset(&A, 0, sizeof(A));
+    A.dens = to_device(w);
+    WalkJob& J = A.job;
+    J.nodes = nodes;
+    J.paths = (uint64_t)paths_per_node;
+    J.bmap = to_device(bmap);
+    J.gp = gauss_params(A.dens);
+    J.dt = (float)dt;
+    J.noise = (float)noise_f32(dt);
+    J.bridge_c = (float)(-1.4426950408889634 / dt);
+    J.exit_test = exit_test;
+    J.kblocks = (uint32_t)(kmax / 3);
+    J.path0 = (uint32_t)path_begin;
+    J.key0 = (uint32_t)seed;
+    J.key1 = (uint32_t)(seed >> 32);
+    J.n_nodes = (uint32_t)n_nodes;
+    A.pool_paths = pool_paths_for(n_nodes * paths_per_node, cu_count);
+    const uint32_t chunks = (uint32_t)((paths_per_node + A.pool_paths - 1) / A.pool_paths);
+    A.seg.pool_base = 0;
+    A.seg.job = nullptr;
+    A.seg.n_nodes = (uint32_t)n_nodes;
+    A.seg.chunks = chunks;
+    A.seg.p_lo = 0;
+    A.seg.p_hi = (uint32_t)paths_per_node;
+    A.total_pools = (uint64_t)n_nodes * chunks;
+    A.kmax = kmax;
+    A.dt = dt;
+    A.sqrt2dt = sqrt(2.0 * dt);
+    A.noise_f32 = noise_f32(dt);
+    return SDD_OK;
+}
+
+// Enqueue set-up, walk and finalize of a prepared estimate whose workspace
+// starts at ws.
+sdd_status run_estimate(sdd_ctx* ctx, WalkArgs& A, char* ws, int32_t prec, int32_t exit_test, double* mean,
+                        double* se, double* sums, sdd_walk_stats* stats, sdd_path_record* per_path,
+                        hipStream_t stream)
+{
+    const int64_t n = A.job.n_nodes;
+    const WalkWorkspace W = walk_workspace(n);
+    A.counter = (unsigned long long*)(ws + W.counter_off);
+    A.job.acc = (NodeAcc*)(ws + W.acc_off);
+    A.job.scale = (const AccScale*)(ws + W.scale_off);
+    A.job.per_path = per_path;
+    unsigned long long* clock0 = (unsigned long long*)(ws + W.clock_off);
+    double vmax = 0.0;
+    const bool host_scale = bmap_host_bound(A.job.bmap, vmax);
+    const AccScale hs = scale_for_bound(vmax);
+    hipError_t e = launch_acc_init(A.job.acc, n, (AccScale*)(ws + W.scale_off), A.job.bmap, host_scale, hs,
+                                   A.counter, clock0, stream);
+    const int kind = exit_test == SDD_EXIT_BRIDGE ? kExitBridge
+                     : exit_test == SDD_EXIT_EXPONENTIAL ? kExitExpo : kExitStep;
+    if (e == hipSuccess) e = launch_walk(A, prec, kind, stream);
+    if (e == hipSuccess)
+        e = launch_finalize(A.job.acc, A.job.scale, n, (double)A.job.paths, mean, se, sums, stats, clock0,
+                            (double)ctx->wall_rate_khz, stream);
+    return from_hip(e);
+}
+
+}  // namespace
 
 sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap, const double* nodes,
                                   int64_t n_nodes, int64_t paths_per_node, int64_t path_begin, double dt,
@@ -83,48 +170,21 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
                                   sdd_walk_stats* stats, sdd_path_record* per_path, void* workspace, size_t ws_bytes,
                                   void* stream)
 {
-    if (!ctx || !nodes || !mean || !workspace) return SDD_EINVAL;
-    sdd_status s = check_density(w);
-    if (s != SDD_OK) return s;
-    if ((s = check_bmap(bmap)) != SDD_OK) return s;
-    if (n_nodes < 1 || paths_per_node < 1 || path_begin < 0) return SDD_EINVAL;
-    if (n_nodes * paths_per_node >= kMaxTickets) return SDD_EINVAL;
-    if (path_begin + paths_per_node > ((int64_t)1 << 32)) return SDD_EINVAL;
-    if (!(dt > 0.0) || !(dt < 1.0)) return SDD_EINVAL;
-    if (prec != SDD_FP32 && prec != SDD_FP64) return SDD_EINVAL;
-    if (exit_test != SDD_EXIT_END_OF_STEP && exit_test != SDD_EXIT_BRIDGE) return SDD_EINVAL;
-    if (!(t_max > 0.0)) t_max = 8.0;
-    if (!is_finite(t_max)) return SDD_EINVAL;
-    double kd = ceil(t_max / dt);
-    if (!(kd >= 1.0) || kd >= (double)(kMaxSteps - 2)) return SDD_EINVAL;
-    kd += fmod(3.0 - fmod(kd, 3.0), 3.0);  // a whole number of three-step Philox blocks
-    const WalkWorkspace W = walk_workspace(n_nodes, paths_per_node, prec);
-    if (ws_bytes < W.bytes) return SDD_ENOSPC;
-    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
-
+    if (!ctx || !workspace) return SDD_EINVAL;
     WalkArgs A;
-    memset(&A, 0, sizeof(A));
-    A.dens = to_device(w);
-    A.bmap = to_device(bmap);
-    A.nodes = nodes;
-    A.n_nodes = n_nodes;
-    A.paths = paths_per_node;
-    A.path_begin = path_begin;
-    A.total = (uint32_t)(n_nodes * paths_per_node);
-    A.kmax = (int32_t)kd;
-    A.dt = dt;
-    A.sqrt2dt = sqrt(2.0 * dt);
-    A.noise_f32 = sqrt(2.0 * dt) * sqrt(2.0 * 0.69314718055994530942);
-    A.bridge = exit_test == SDD_EXIT_BRIDGE ? 1 : 0;
-    A.key0 = (uint32_t)seed;
-    A.key1 = (uint32_t)(seed >> 32);
-    char* ws = (char*)workspace;
-    A.pq = (void*)(ws + W.pq_off);
-    A.info = (uint32_t*)(ws + W.info_off);
-    A.counter = (unsigned long long*)(ws + W.counter_off);
-    A.per_path = per_path;
-    long long* node_tot = (long long*)(ws + W.node_tot_off);
-    return from_hip(launch_walk(A, prec, mean, se, sums, stats, node_tot, (hipStream_t)stream));
+    sdd_status s = prepare_estimate(w, bmap, nodes, n_nodes, paths_per_node, path_begin, dt, seed, prec, t_max,
+                                    exit_test, mean, ctx->cu_count, A);
+    if (s != SDD_OK) return s;
+    if (ws_bytes < walk_workspace(n_nodes).bytes) return SDD_ENOSPC;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    return run_estimate(ctx, A, (char*)workspace, prec, exit_test, mean, se, sums, stats, per_path,
+                        (hipStream_t)stream);
+}
+
+sdd_status sdd_walk_status(const sdd_walk_stats* stats)
+{
+    if (!stats) return SDD_EINVAL;
+    return stats->capped > 0 ? SDD_WARN_CAPPED : SDD_OK;
 }
 
 int64_t sdd_layout_node_count(const sdd_layout* L, int32_t k)

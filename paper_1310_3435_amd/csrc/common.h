@@ -92,7 +92,9 @@ __device__ inline void term_f64(const Density& D, int t, double xi, double eta, 
 
 // w and grad w in double.  KIND >= 0: a single term of that kind (known at
 // compile time); KIND = kAnyTerms: the general sum over D.n_terms terms.
+// kGaussSum (float walks only): a sum of Gaussian bumps, gauss_sum_drift.
 constexpr int kAnyTerms = -1;
+constexpr int kGaussSum = -2;
 
 template <int KIND = kAnyTerms>
 __device__ inline void density_grad(const Density& D, double xi, double eta, double& w, double& gx, double& gy)
@@ -168,20 +170,48 @@ __device__ inline void term_f32(const Density& D, int t, float xi, float eta, fl
     }
 }
 
-// drift b = grad w / w in float for a single term, written so that the
-// amplitude folds into the exponent and 1/w into one common factor h with
-// b = h (d_xi, d_eta) or b = h (nx, ny).
+// Float parameters of a sum of up to SDD_MAX_TERMS Gaussian bumps in the
+// form gauss_sum_drift reads: amp e^{-c r^2} = 2^(k2 r^2 + la), m2c = -2c.
+struct GaussParams {
+    int32_t n_terms;
+    float base;
+    float cx[SDD_MAX_TERMS], cy[SDD_MAX_TERMS], k2[SDD_MAX_TERMS], la[SDD_MAX_TERMS], m2c[SDD_MAX_TERMS];
+};
+
+// drift b = grad w / w in float of w = base + sum of Gaussian bumps, the
+// terms taken in order.  The walk of an estimate call (parameters in
+// scalar registers) and the request server's walk (parameters per lane)
+// both evaluate exactly this sequence of operations, so a request walks
+// bit for bit the paths an estimate call walks.
+__device__ __forceinline__ void gauss_sum_drift(int n, float base, const float* cx, const float* cy, const float* k2,
+                                                const float* la, const float* m2c, float x, float y, float& bx,
+                                                float& by)
+{
+    float W = base, Gx = 0.0f, Gy = 0.0f;
+#pragma unroll
+    for (int q = 0; q < SDD_MAX_TERMS; ++q) {
+        if (q < n) {
+            const float dx = x - cx[q], dy = y - cy[q];
+            const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(k2[q], __builtin_fmaf(dx, dx, dy * dy), la[q]));
+            W += e;
+            const float h = m2c[q] * e;
+            Gx = __builtin_fmaf(h, dx, Gx);
+            Gy = __builtin_fmaf(h, dy, Gy);
+        }
+    }
+    const float iw = __builtin_amdgcn_rcpf(W);
+    bx = Gx * iw;
+    by = Gy * iw;
+}
+
+// drift b = grad w / w in float for a single ring, sech^2 or sin^2 term,
+// written so that the amplitude folds into the exponent and 1/w into one
+// common factor h with b = h (d_xi, d_eta) or b = h (nx, ny).
 template <int KIND>
 __device__ inline void drift1_f32(const Density& D, float xi, float eta, float& bx, float& by)
 {
     const float dx = xi - D.fcx[0], dy = eta - D.fcy[0];
-    if (KIND == SDD_TERM_GAUSS) {
-        const float r2 = __builtin_fmaf(dx, dx, dy * dy);
-        const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(D.fk2[0], r2, D.fla[0]));
-        const float h = D.fm2c[0] * e * __builtin_amdgcn_rcpf(D.fbase + e);
-        bx = h * dx;
-        by = h * dy;
-    } else if (KIND == SDD_TERM_RING) {
+    if (KIND == SDD_TERM_RING) {
         // r^2 clamped away from 0: at the centre d_xi = d_eta = 0 and b = 0
         const float r2 = fmaxf(__builtin_fmaf(dx, dx, dy * dy), 1e-30f);
         const float rinv = __builtin_amdgcn_rsqf(r2);

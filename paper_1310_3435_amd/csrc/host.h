@@ -7,10 +7,12 @@
 
 #include "common.h"
 #include "sdd.h"
+#include "walk.h"
 
 struct sdd_ctx {
     int device;
     int cu_count;
+    int wall_rate_khz;  // rate of the device wall clock (wall_clock64)
 };
 
 namespace sdd {
@@ -99,8 +101,53 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 inline sdd_status from_hip(hipError_t e) { return e == hipSuccess ? SDD_OK : SDD_EDEVICE; }
 
-// tickets (node, path) are 32-bit; keep clear of the top for the batch fetches
-constexpr int64_t kMaxTickets = ((int64_t)1 << 32) - ((int64_t)1 << 24);
+// Nodes and paths per node are counter words of 32 bits; the node sums are
+// exact for up to 2^32 paths per node.
+constexpr int64_t kMaxNodes = ((int64_t)1 << 32) - 1;
+constexpr int64_t kMaxPathsPerNode = ((int64_t)1 << 32) - 1;
+
+// Noise factor of a float step: sqrt(2 dt) sqrt(2 ln 2) (the float normals
+// come scaled by 1/sqrt(2 ln 2)).
+inline double noise_f32(double dt) { return sqrt(2.0 * dt) * sqrt(2.0 * 0.69314718055994530942); }
+
+// Step cap ceil(t_max/dt) rounded up to whole three-step Philox blocks; -1
+// when it does not fit the 28-bit step count.
+inline int32_t step_cap(double t_max, double dt)
+{
+    double kd = ceil(t_max / dt);
+    if (!(kd >= 1.0) || kd >= (double)(((int64_t)1 << 28) - 3)) return -1;
+    kd += fmod(3.0 - fmod(kd, 3.0), 3.0);
+    return (int32_t)kd;
+}
+
+// Paths per pool of a walk launch: 64, or up to 256 when the launch has at
+// least 8 pools of that size for every wave a device of cu_count CUs keeps
+// (16 per CU).  Results do not depend on it.
+inline uint32_t pool_paths_for(int64_t total_paths, int cu_count)
+{
+    const int64_t waves = (int64_t)(cu_count > 0 ? cu_count : 256) * 16;
+    int64_t k = total_paths / (waves * kPoolPaths * 8);
+    if (k < 1) k = 1;
+    if (k > (int64_t)(kMaxPoolPaths / kPoolPaths)) k = kMaxPoolPaths / kPoolPaths;
+    return (uint32_t)(k * kPoolPaths);
+}
+
+// Float Gaussian-sum parameters of a density whose terms are all GAUSS.
+inline GaussParams gauss_params(const Density& D)
+{
+    GaussParams G;
+    memset(&G, 0, sizeof(G));
+    G.n_terms = D.n_terms;
+    G.base = D.fbase;
+    for (int t = 0; t < D.n_terms; ++t) {
+        G.cx[t] = D.fcx[t];
+        G.cy[t] = D.fcy[t];
+        G.k2[t] = D.fk2[t];
+        G.la[t] = D.fla[t];
+        G.m2c[t] = D.fm2c[t];
+    }
+    return G;
+}
 
 
 }  // namespace sdd

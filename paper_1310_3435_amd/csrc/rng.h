@@ -74,6 +74,13 @@ __device__ __forceinline__ float uniform23(uint32_t q, float)
 }
 __device__ __forceinline__ double uniform23(uint32_t q, double) { return ((double)(q & 0x007fffffu) + 0.5) * 0x1p-23; }
 
+// Exponential time stepping (Sec. 2.2): the length of step 3m + j is an
+// exponential variate with mean dt (rate 1/dt), tau = -ln(u) dt, u from
+// word j of the block of counter (m, p, g, 2) as uniform23 forms it.
+// Float: c = dt ln 2, so that tau = -log2(u) c on the transcendental unit.
+__device__ __forceinline__ float expo_step(uint32_t q, float c) { return -__builtin_amdgcn_logf(uniform23(q, 0.0f)) * c; }
+__device__ __forceinline__ double expo_step(uint32_t q, double dt) { return -log(uniform23(q, 0.0)) * dt; }
+
 // Box-Muller pair (z0, z1) = sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b).
 // The float version returns the pair scaled by 1/sqrt(2 ln 2),
 // sqrt(-log2 u_a) (cos, sin), and the caller folds sqrt(2 ln 2) into the

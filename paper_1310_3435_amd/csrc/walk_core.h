@@ -1,0 +1,409 @@
+// walk_core.h -- the interface walk kernel (gfx950), shared by estimate
+// calls (walk.hip) and the request server (serve.hip).
+//
+// A persistent grid of wavefronts draws pools of consecutive paths of one
+// node (64 to 256, per launch) from a device counter.  One lane walks one path; when its
+// path exits, the lane takes the wave's next path, whatever node it
+// belongs to, so lanes stay busy until the pools run out.  A loop iteration
+// is one Philox block, i.e. three Euler-Maruyama steps (Sec. 2.2) with an
+// exit test after each; a path always starts a block.  With the Brownian
+// bridge the step also exits, with the bridge's conditional probability,
+// when both its ends are inside; with exponential time stepping every step
+// has an exponentially distributed length and the bridge test (rng.h).
+//
+// A finished path leaves its last step's ends P, Q and its step count in a
+// per-wave queue in LDS.  Once the queue holds 64 entries the wave empties
+// it with all lanes at once: each lane projects one path's last step onto
+// the boundary in double (first crossing; the nearest boundary point for a
+// capped path), evaluates the boundary map there (eq. (7a)) and turns the
+// value, its square and the step count into integer contributions to the
+// node's exact sums (walk.h); the wave adds them up per node and one lane
+// per node adds the totals with 64-bit atomics.  The walk keeps no
+// double-precision state, the double work runs on full waves, and the sums
+// do not depend on which lane walked which path or when.
+#pragma once
+
+#include "common.h"
+#include "rng.h"
+#include "walk.h"
+
+namespace sdd {
+
+constexpr int kWavesPerBlock = kWalkBlock / kWave;
+
+// ------------------------------------------------------- exit processing
+
+// Sum of v over the wave (every lane gets it).
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+{
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+// A finished path's contribution to its node's sums, kept in the lane
+// between its exit processing and the per-node reduction.
+struct PathValue {
+    double x, y;       // boundary value at the exit point
+    uint32_t steps;
+    NodeAcc* acc;      // the node's sums (the reduction key)
+};
+
+// Word q of a path's contribution: q = 2j, 2j+1 the low and high limbs of
+// the j-th of x, y, x^2, y^2 scaled by the job's 2^F (walk.h); q = 8 the
+// step count.
+__device__ __forceinline__ unsigned long long acc_word(const PathValue& v, const AccScale& S, int q)
+{
+    if (q == 8) return v.steps;
+    const int j = q >> 1;
+    const double u = j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.x * v.x : v.y * v.y;
+    const long long n = (long long)rint(u * S.s[j >> 1]);  // |n| <= 2^60
+    return (q & 1) ? (unsigned long long)(n >> 31) : (unsigned long long)(n & 0x7fffffffll);
+}
+
+// Exit point and boundary value of one finished path.  Writes the path's
+// record in parity mode and counts a capped path.
+template <typename R>
+__device__ __forceinline__ PathValue finish_path(const WalkJob& J, const ExitEntry<R>& e)
+{
+    const double px = e.px, py = e.py, qx = e.qx, qy = e.qy;
+    const uint32_t w = e.info;
+    const bool capped = (w & kInfoCapped) != 0;
+    double ex, ey;
+    int side;
+    if (w & kInfoBridged) {
+        // bridged exit: the end of the step moved onto the wall it crossed
+        side = (int)((w >> kInfoSideShift) & 3u);
+        ex = side == 0 ? 0.0 : side == 1 ? 1.0 : qx;
+        ey = side == 2 ? 0.0 : side == 3 ? 1.0 : qy;
+    } else {
+        side = capped ? nearest_side(qx, qy, ex, ey) : exit_point(px, py, qx, qy, ex, ey);
+    }
+    PathValue v;
+    bmap_eval(J.bmap, side, ex, ey, v.x, v.y);
+    v.steps = w & kInfoSteps;
+    v.acc = J.acc + e.g;
+    if (capped) atomicAdd(&v.acc->capped, 1ull);
+    if (J.per_path) {
+        sdd_path_record* rec = J.per_path + (size_t)e.g * J.paths + e.p;
+        rec->exit_xi = ex;
+        rec->exit_eta = ey;
+        rec->steps = w & kInfoSteps;
+        rec->side = side;
+        rec->capped = capped ? 1 : 0;
+    }
+    return v;
+}
+
+// A wave's exit queue is a ring of kQueue entries in LDS; it is emptied up
+// to 64 entries at a time, lane i finishing entry head + i.  The entries'
+// contributions are then summed per node across the wave (integer sums:
+// exact, in any order), and one lane per node adds them to the node's sums,
+// so a node's cache line takes one atomic per word per drain instead of one
+// per path.  The words are reduced one at a time, which keeps the drain's
+// registers few.
+constexpr uint32_t kQueue = 2 * kWave;
+
+template <typename R, bool LANE>
+__device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R>* queue, uint32_t head,
+                                            uint32_t count)
+{
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const bool have = lane < count;
+    PathValue v{ 0.0, 0.0, 0u, nullptr };
+    AccScale S{ { 1.0, 1.0 } };
+    if (have) {
+        const ExitEntry<R> e = queue[(head + lane) & (kQueue - 1)];
+        if constexpr (LANE) {
+            const WalkJob& J = *A.segs[e.seg].job;
+            v = finish_path(J, e);
+            S = *J.scale;
+        } else {
+            v = finish_path(A.job, e);
+            S = *A.job.scale;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    uint64_t todo = __ballot(have);
+    while (todo != 0) {
+        const int leader = (int)__builtin_ctzll(todo);
+        const unsigned long long key = __shfl((unsigned long long)v.acc, leader, kWave);
+        const bool mine = have && (unsigned long long)v.acc == key;
+        todo &= ~__ballot(mine);
+        unsigned long long* dst = (unsigned long long*)key;
+#pragma unroll 1
+        for (int q = 0; q < 9; ++q) {
+            const unsigned long long sum = wave_sum(mine ? acc_word(v, S, q) : 0ull);
+            // words 0..7 are lo[0], hi[0], ..., in NodeAcc order lo[4], hi[4], steps
+            if ((int)lane == leader) atomicAdd(dst + (q == 8 ? 8 : (q & 1) * 4 + (q >> 1)), sum);
+        }
+    }
+}
+
+// ------------------------------------------------------------ the walk
+
+template <int KIND>
+__device__ __forceinline__ void drift(const WalkArgs& A, float x, float y, float& bx, float& by)
+{
+    if constexpr (KIND == kGaussSum) {
+        const GaussParams& G = A.job.gp;
+        gauss_sum_drift(G.n_terms, G.base, G.cx, G.cy, G.k2, G.la, G.m2c, x, y, bx, by);
+    } else {
+        drift_f32<KIND>(A.dens, x, y, bx, by);
+    }
+}
+template <int KIND>
+__device__ __forceinline__ void drift(const WalkArgs& A, double x, double y, double& bx, double& by)
+{
+    drift_f64<KIND>(A.dens, x, y, bx, by);
+}
+
+// Noise factor of one step: sqrt(2 dt) times the normals' scale (rng.h).
+__device__ __forceinline__ float noise_scale(const WalkArgs& A, float) { return (float)A.noise_f32; }
+__device__ __forceinline__ double noise_scale(const WalkArgs& A, double) { return A.sqrt2dt; }
+// Constant of the bridge test: -log2(e)/dt in float, dt in double.
+__device__ __forceinline__ float bridge_const(double dt, float) { return (float)(-1.4426950408889634 / dt); }
+__device__ __forceinline__ double bridge_const(double dt, double) { return dt; }
+// Exponential steps: tau = -log2(u) (dt ln 2) in float, -ln(u) dt in double;
+// then the noise factor and the bridge constant of that step.
+__device__ __forceinline__ float expo_const(double dt, float) { return (float)(dt * 0.69314718055994530942); }
+__device__ __forceinline__ double expo_const(double dt, double) { return dt; }
+__device__ __forceinline__ float expo_noise(float tau) { return __builtin_amdgcn_sqrtf(tau * 2.7725887222397812f); }
+__device__ __forceinline__ double expo_noise(double tau) { return sqrt(2.0 * tau); }
+__device__ __forceinline__ float expo_bridge(float tau) { return -kLog2e * __builtin_amdgcn_rcpf(tau); }
+__device__ __forceinline__ double expo_bridge(double tau) { return tau; }
+
+// Segment of pool q (server): the last segment with pool_base <= q.
+__device__ __forceinline__ int find_segment(const WalkSeg* segs, int nseg, uint64_t q)
+{
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (segs[mid].pool_base <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// R: walk precision.  KIND: density kind (common.h).  EXIT: ExitKind.
+// PIPE: each iteration also computes the next three steps' Philox block
+// (it depends on the counters only), so that waves have independent work
+// to overlap with the steps' latency; the random numbers, and hence all
+// results, are the same either way.  LANE: per-lane job parameters
+// (request server; float Gaussian sums), else wave-uniform ones in A.
+template <typename R, int KIND, int EXIT, bool PIPE, bool LANE>
+__global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
+{
+    static_assert(!LANE || (KIND == kGaussSum && EXIT == kExitLane), "the server walks float Gaussian sums");
+    __shared__ ExitEntry<R> queues[kWavesPerBlock][kQueue];
+    ExitEntry<R>* queue = queues[threadIdx.x / kWave];
+    uint32_t qh = 0, qn = 0;  // first entry and entries in the wave's queue (wave-uniform)
+    const int lane = threadIdx.x & (kWave - 1);
+
+    // wave-uniform pool: node, next path, end
+    uint32_t pool_g = 0, pool_p = 0, pool_end = 0, pool_seg = 0;
+    bool exhausted = false;
+    // lane state
+    bool live = false;
+    uint32_t g = 0, p = 0, seg = 0, pc = 0;  // node, path, segment, path counter word
+    uint4 rc = make_uint4(0, 0, 0, 0);      // Philox block of the lane's current steps (PIPE)
+    R X = 0, Y = 0;
+    uint32_t m = 0;  // Philox block index: steps 3m .. 3m+2
+    // step parameters: wave-uniform, or the lane's job
+    R dt = (R)A.dt, sd = noise_scale(A, R(0)), bc = bridge_const(A.dt, R(0));
+    const R ec = expo_const(A.dt, R(0));
+    uint32_t mmax = (uint32_t)(A.kmax / 3);
+    uint32_t key0 = A.job.key0, key1 = A.job.key1;
+    bool lbridge = false;
+    GaussParams lg;
+    if constexpr (LANE) {
+        lg.n_terms = 0;
+        lg.base = 1.0f;
+#pragma unroll
+        for (int q = 0; q < SDD_MAX_TERMS; ++q) lg.cx[q] = lg.cy[q] = lg.k2[q] = lg.la[q] = lg.m2c[q] = 0.0f;
+    }
+
+    for (;;) {
+        // hand the wave's pools to idle lanes, in lane order
+        uint64_t need = __ballot(!live);
+        while (need != 0 && !exhausted) {
+            if (pool_p == pool_end) {
+                unsigned long long q = 0;
+                if (lane == 0) q = atomicAdd(A.counter, 1ull);
+                q = __shfl(q, 0, kWave);
+                // wave-uniform: keep it in scalar registers
+                q = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(q >> 32)) << 32) |
+                    __builtin_amdgcn_readfirstlane((uint32_t)q);
+                if (q >= A.total_pools) {
+                    exhausted = true;
+                    break;
+                }
+                int si = 0;
+                if constexpr (LANE) si = find_segment(A.segs, A.nseg, q);
+                const WalkSeg& S = LANE ? A.segs[si] : A.seg;
+                // pools go round the nodes (pool j of node g is local pool
+                // j n + g), so that waves working at the same time add into
+                // different nodes' sums
+                const uint64_t local = q - S.pool_base;
+                const uint64_t c = local / S.n_nodes;
+                pool_g = (uint32_t)(local - c * S.n_nodes);
+                pool_p = S.p_lo + (uint32_t)c * A.pool_paths;
+                pool_end = min(S.p_hi, pool_p + A.pool_paths);
+                pool_seg = (uint32_t)si;
+            }
+            const uint32_t avail = pool_end - pool_p;
+            const uint32_t want = (uint32_t)__popcll(need);
+            const uint32_t take = want < avail ? want : avail;
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!live && rank < take) {
+                g = pool_g;
+                p = pool_p + rank;
+                seg = pool_seg;
+                const WalkJob& J = LANE ? *A.segs[seg].job : A.job;
+                if constexpr (LANE) {
+                    lg = J.gp;
+                    dt = J.dt;
+                    sd = J.noise;
+                    bc = J.bridge_c;
+                    lbridge = J.exit_test == SDD_EXIT_BRIDGE;
+                    mmax = J.kblocks;
+                    key0 = J.key0;
+                    key1 = J.key1;
+                }
+                pc = J.path0 + p;
+                const double nx0 = J.nodes[2 * (size_t)g], ny0 = J.nodes[2 * (size_t)g + 1];
+                if (nx0 > 0.0 && nx0 < 1.0 && ny0 > 0.0 && ny0 < 1.0) {
+                    X = (R)nx0;
+                    Y = (R)ny0;
+                    m = 0;
+                    live = true;
+                    if constexpr (PIPE) rc = philox(0u, pc, g, 0u, key0, key1);
+                } else {
+                    // a node off the open square walks nothing: NaN result
+                    J.acc[g].invalid = 1u;
+                    if (J.per_path) {
+                        sdd_path_record* rec = J.per_path + (size_t)g * J.paths + p;
+                        rec->exit_xi = rec->exit_eta = __builtin_nan("");
+                        rec->steps = 0;
+                        rec->side = -1;
+                        rec->capped = 0;
+                    }
+                }
+            }
+            pool_p += take;
+            need = __ballot(!live);
+        }
+        if (__ballot(live) == 0) break;
+
+        uint4 r;
+        if constexpr (PIPE) {
+            r = rc;
+            rc = philox(m + 1u, pc, g, 0u, key0, key1);
+        } else {
+            r = philox(m, pc, g, 0u, key0, key1);
+        }
+        // step lengths, noise factors and bridge constants of the three steps
+        R dA = dt, dB = dt, dC = dt, sA = sd, sB = sd, sC = sd, cA = bc, cB = bc, cC = bc;
+        if constexpr (EXIT == kExitExpo) {
+            const uint4 e = philox(m, pc, g, 2u, key0, key1);
+            dA = expo_step(e.x, ec);
+            dB = expo_step(e.y, ec);
+            dC = expo_step(e.z, ec);
+            sA = expo_noise(dA);
+            sB = expo_noise(dB);
+            sC = expo_noise(dC);
+            cA = expo_bridge(dA);
+            cB = expo_bridge(dB);
+            cC = expo_bridge(dC);
+        }
+        R bx, by, z0, z1;
+        // step 3m
+        normals(field_hi(r.x, R(0)), field_hi(r.y, R(0)), z0, z1);
+        if constexpr (LANE) gauss_sum_drift(lg.n_terms, lg.base, lg.cx, lg.cy, lg.k2, lg.la, lg.m2c, X, Y, bx, by);
+        else drift<KIND>(A, X, Y, bx, by);
+        const R XA = fmar(sA, z0, fmar(bx, dA, X));
+        const R YA = fmar(sA, z1, fmar(by, dA, Y));
+        // step 3m+1
+        normals(field_hi(r.z, R(0)), field_hi(r.w, R(0)), z0, z1);
+        if constexpr (LANE) gauss_sum_drift(lg.n_terms, lg.base, lg.cx, lg.cy, lg.k2, lg.la, lg.m2c, XA, YA, bx, by);
+        else drift<KIND>(A, XA, YA, bx, by);
+        const R XB = fmar(sB, z0, fmar(bx, dB, XA));
+        const R YB = fmar(sB, z1, fmar(by, dB, YA));
+        // step 3m+2
+        normals(field_lo(r.x, r.y, R(0)), field_lo(r.z, r.w, R(0)), z0, z1);
+        if constexpr (LANE) gauss_sum_drift(lg.n_terms, lg.base, lg.cx, lg.cy, lg.k2, lg.la, lg.m2c, XB, YB, bx, by);
+        else drift<KIND>(A, XB, YB, bx, by);
+        const R XC = fmar(sC, z0, fmar(bx, dC, XB));
+        const R YC = fmar(sC, z1, fmar(by, dC, YB));
+
+        // the step cap is a whole number of blocks, so it can only fall
+        // after step 3m+2
+        const bool outA = outside(XA, YA);
+        const bool outB = outside(XB, YB);
+        const bool outC = outside(XC, YC);
+        bool exA = outA, exB = outB, exC = outC;
+        bool test = EXIT == kExitBridge || EXIT == kExitExpo;
+        if constexpr (EXIT == kExitLane) test = __ballot(live && lbridge) != 0;  // some lane's job asks for it
+        if (test) {
+            const bool mine = EXIT == kExitLane ? lbridge : true;
+            const R PA = bridge_prob(X, Y, XA, YA, cA);
+            const R PB = bridge_prob(XA, YA, XB, YB, cB);
+            const R PC = bridge_prob(XB, YB, XC, YC, cC);
+            const bool may = (!outA && bridge_may_exit(PA)) || (!outB && bridge_may_exit(PB)) ||
+                             (!outC && bridge_may_exit(PC));
+            if (__ballot(live && mine && may) != 0) {
+                // some lane is near a wall: draw the bridge block (wave-uniform branch)
+                const uint4 q = philox(m, pc, g, 1u, key0, key1);
+                exA = outA || (mine && uniform23(q.x, R(0)) < PA);
+                exB = outB || (mine && uniform23(q.y, R(0)) < PB);
+                exC = outC || (mine && uniform23(q.z, R(0)) < PC);
+            }
+        }
+        const bool fin = live && (exA || exB || exC || (m + 1u >= mmax));
+        const uint64_t fm = __ballot(fin);
+        if (fm != 0) {
+            const uint32_t nf = (uint32_t)__popcll(fm);
+            if (fin) {
+                // the first exiting step's ends
+                const R px = exA ? X : (exB ? XA : XB), py = exA ? Y : (exB ? YA : YB);
+                const R qx = exA ? XA : (exB ? XB : XC), qy = exA ? YA : (exB ? YB : YC);
+                uint32_t w = 3u * m + (exA ? 1u : (exB ? 2u : 3u));
+                if (!(exA || exB || exC))
+                    w |= kInfoCapped;
+                else if (EXIT != kExitStep && !(exA ? outA : (exB ? outB : outC)))
+                    w |= kInfoBridged | (bridge_side(px, py, qx, qy) << kInfoSideShift);
+                const uint32_t slot =
+                    qh + qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(fm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fm, 0u));
+                ExitEntry<R>& E = queue[slot & (kQueue - 1)];
+                E.px = px;
+                E.py = py;
+                E.qx = qx;
+                E.qy = qy;
+                E.info = w;
+                E.g = g;
+                E.p = p;
+                E.seg = seg;
+                live = false;
+            }
+            qn += nf;
+        }
+        // finished and idle lanes carry garbage until their next start
+        X = XC;
+        Y = YC;
+        ++m;
+        if (qn >= (uint32_t)kWave) {  // at most 127 entries: room for the next iteration's 64
+            drain_exits<R, LANE>(A, queue, qh, kWave);
+            qh = (qh + kWave) & (kQueue - 1);
+            qn -= kWave;
+        }
+    }
+    while (qn) {
+        const uint32_t c = qn < (uint32_t)kWave ? qn : (uint32_t)kWave;
+        drain_exits<R, LANE>(A, queue, qh, c);
+        qh = (qh + c) & (kQueue - 1);
+        qn -= c;
+    }
+}
+
+}  // namespace sdd

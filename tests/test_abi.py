@@ -39,22 +39,50 @@ def test_host_only_entry_points_work_without_a_gpu():
     assert sdd.sdd_version() >= 100
     assert L.sdd_status_string(-1) == b"invalid argument"
     # every status of the header has its own message
-    msgs = [L.sdd_status_string(c) for c in (0, -1, -2, -3, -4, -5, -6)]
-    assert len(set(msgs)) == 7 and b"unknown status" not in msgs
+    msgs = [L.sdd_status_string(c) for c in (0, 1, -1, -2, -3, -4, -5, -6)]
+    assert len(set(msgs)) == 8 and b"unknown status" not in msgs
     assert L.sdd_status_string(-99) == b"unknown status"
     assert sdd.sdd_layout_node_count({"nx": 257, "ny": 257, "sx": 4, "sy": 4}, 63) == 1521
     assert sdd.sdd_layout_node_count({"nx": 1025, "ny": 1025, "sx": 8, "sy": 8}, 32) == 3633
     assert sdd.sdd_layout_node_count({"nx": 65, "ny": 33, "sx": 2, "sy": 1}, 15) == 15
     with pytest.raises(sdd.SddError):
         sdd.sdd_layout_node_count({"nx": 64, "ny": 33, "sx": 2, "sy": 1}, 15)
-    assert sdd.sdd_workspace_bytes(1521, 10000) > 0
+    # the walk's workspace is the node sums: 96 bytes per node and a header,
+    # whatever the paths per node
+    assert sdd.sdd_workspace_bytes(1521, 10000) == sdd.sdd_workspace_bytes(1521, 2**32 - 1) >= 1521 * 96
+    assert sdd.sdd_workspace_bytes(1521, 10000) < 1521 * 96 + 1024
     assert sdd.sdd_workspace_bytes(0, 10000) == 0
+    assert sdd.sdd_workspace_bytes(10, 0) == 0 and sdd.sdd_workspace_bytes(10, 2**32) == 0
     assert sdd.sdd_subdomain_workspace_bytes({"nx": 65, "ny": 33, "sx": 2, "sy": 1}) > 65 * 33 * 16
     import ctypes as C
     L65 = sdd.make_layout({"nx": 65, "ny": 49, "sx": 4, "sy": 3})
     assert L.sdd_quality_workspace_bytes(65, 49) > 0 and L.sdd_quality_workspace_bytes(1, 49) == 0
     assert L.sdd_smooth_workspace_bytes(C.byref(L65)) == 65 * 49 * 16
     assert L.sdd_smooth_interfaces_workspace_bytes(C.byref(L65)) >= (3 * 49 + 2 * 65) * 16
+
+
+def test_walk_status_reads_host_stats():
+    # a host function on a host struct: SDD_WARN_CAPPED when paths were capped
+    import warnings
+
+    import numpy as np
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    L = sdd.lib()
+    st = sdd.sdd_walk_stats(100, 10, 0, 1.5)
+    assert L.sdd_walk_status(ctypes.byref(st)) == sdd.SDD_OK
+    st.capped = 3
+    assert L.sdd_walk_status(ctypes.byref(st)) == sdd.SDD_WARN_CAPPED == 1
+    assert L.sdd_walk_status(None) == sdd.SDD_EINVAL
+    # the binding's view of device stats (here a CPU tensor of the same layout)
+    raw = np.array([100, 10, 3, 0], dtype=np.int64)
+    raw[3:4] = np.array([2.5]).view(np.int64)
+    with warnings.catch_warnings(record=True) as w:
+        warnings.simplefilter("always")
+        v = sdd.walk_stats(torch.from_numpy(raw))
+    assert v == {"steps": 100, "paths": 10, "capped": 3, "t_stoc_ms": 2.5}
+    assert any(issubclass(x.category, sdd.SddCappedWarning) for x in w)
 
 
 def test_struct_layouts_match_the_header():
@@ -64,6 +92,9 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(sdd.sdd_bmap) == 8 + 64 + 8
     assert ctypes.sizeof(sdd.sdd_layout) == 16
     assert sdd.PATH_RECORD.itemsize == 32
+    assert ctypes.sizeof(sdd.sdd_walk_stats) == 32
+    # result: status, pad, 4 int64, max_se, 3 clock times, 4 stage times
+    assert ctypes.sizeof(sdd.sdd_result) == 8 + 4 * 8 + 8 + 3 * 8 + 4 * 8
     # request: density, map, layout, 4 int32, dt, se_target, paths, seed, t_max
     assert ctypes.sizeof(sdd.sdd_request) == (16 + 4 * 64) + (8 + 64 + 8) + 16 + 16 + 5 * 8
 

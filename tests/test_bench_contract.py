@@ -13,17 +13,17 @@ sys.path.insert(0, ROOT)
 
 def test_committed_traffic_profile_matches_the_kernel():
     import bench
-    t = bench.traffic_from_profile("ring_fp32_4x4x65")
+    t = bench.traffic_from_profile("annulus_fp32_8x8x129")
     # None means the kernel changed since the counters were taken: re-profile
-    assert t is not None, "profiles/walk_ring_fp32_4x4x65_traffic.txt is stale for the current kernel"
-    # at least the algorithmic bytes: 20 B per path, 1521 nodes x 1e4 paths
-    assert t >= 20 * 1521 * 10000
+    assert t is not None, "profiles/walk_annulus_fp32_8x8x129_traffic.txt is stale for the current kernel"
+    # at least the algorithmic bytes: the node table and the node sums
+    assert t >= bench.WALK_BYTES_PER_NODE * 3633
 
 
 def test_source_hash_ignores_comments(tmp_path):
     import bench
     src = os.path.join(ROOT, "paper_1310_3435_amd", "csrc")
-    for f in ("walk.hip", "walk.h", "common.h", "rng.h"):
+    for f in ("walk.hip", "walk.h", "walk_core.h", "common.h", "rng.h"):
         text = open(os.path.join(src, f)).read()
         (tmp_path / f).write_text("// a comment\n" + text.replace("\n", "\n  ") + "\n/* another */\n")
     assert bench.kernel_source_hash(str(tmp_path)) == bench.kernel_source_hash()

@@ -131,7 +131,7 @@ def test_bad_exit_test_is_rejected(ctx):
     B = sdd.Bmap({"kind": "identity"}, ctx)
     mean = torch.empty((1, 2), dtype=torch.float64, device="cuda")
     ws = ctx.workspace(sdd.sdd_workspace_bytes(1, 4, "fp64"))
-    for bad in (2, -1):
+    for bad in (3, -1):   # 0, 1, 2: end of step, bridge, exponential stepping
         rc = sdd.lib().sdd_interface_estimate(ctx.h, C.byref(D), C.byref(B.s), nodes.data_ptr(), 1, 4, 0, 1e-3,
                                               C.c_uint64(1), 0, 8.0, bad, mean.data_ptr(), None, None, None, None,
                                               ws.data_ptr(), ws.numel(), None)

@@ -180,11 +180,13 @@ def test_capped_request_matches_the_oracle(ctx, ref):
         out = srv.wait(srv.submit(req))
     finally:
         srv.close()
-    assert out["status"] == 0 and out["paths_per_node"] == 2048
+    # done, with a warning: some paths stopped at the cap
+    assert out["status"] == sdd.SDD_WARN_CAPPED and out["paths_per_node"] == 2048
     cfg = dict(req, prec="fp32")
     r32 = ref.pipeline(cfg)
     est = r32["est"]
     assert est["capped"] > 0.3 * est["paths"]
+    assert out["capped"] == pytest.approx(est["capped"], rel=1e-3)
     r64 = ref.pipeline(dict(cfg, prec="fp64"))
     se = r64["est"]["se"].max()
     d32 = np.abs(out["mesh"] - r32["mesh"]).max()
@@ -193,3 +195,42 @@ def test_capped_request_matches_the_oracle(ctx, ref):
     assert out["steps"] == pytest.approx(est["steps"], rel=1e-4)
     assert d32 <= 0.05 * se
     assert np.abs(out["mesh"] - r64["mesh"]).max() <= 3 * se
+
+
+def test_served_request_equals_the_estimate_call_bitwise(ctx):
+    """One walk implementation: a served float request walks exactly the
+    paths of an sdd_interface_estimate call with the same inputs (path 0 at
+    counter 0, N = the request's paths per node), its node sums are exact,
+    so the fill and solves downstream give the same mesh bit for bit.  The
+    request reports its stage times."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    for exit_test in ("step", "bridge"):
+        req = dict(small_request(seed=61, n=65, s=4,
+                                 bumps=[{"kind": "gauss", "amp": 6.0, "coef": 60.0, "cx": 0.4, "cy": 0.55},
+                                        {"kind": "gauss", "amp": 12.0, "coef": 150.0, "cx": 0.7, "cy": 0.3}]),
+                   exit_test=exit_test)
+        srv = sdd.Server(ctx, hbm_budget_bytes=64 << 20, max_slots=4)
+        try:
+            say(f"serve: one {exit_test} request")
+            out = srv.wait(srv.submit(req))
+        finally:
+            srv.close()
+        assert out["status"] == 0
+        N = out["paths_per_node"]
+        assert N % 1024 == 0 and N > 1024
+        assert out["t_stoc_ms"] > 0 and out["t_fill_ms"] > 0 and out["t_sub_ms"] > 0 and out["t_queue_ms"] >= 0
+        say(f"  N {N}, T_stoc {out['t_stoc_ms']:.1f} ms, T_fill {out['t_fill_ms']:.2f} ms, "
+            f"T_sub {out['t_sub_ms']:.2f} ms")
+        L = req["layout"]
+        nodes = sdd.sdd_layout_nodes(ctx, L, req["k"], "uniform", req["density"])
+        est = sdd.sdd_interface_estimate(ctx, req["density"], req["bmap"], nodes, N, req["dt"], req["seed"], "fp32",
+                                         exit_test=exit_test)
+        vert, horiz = sdd.sdd_fill_interfaces(ctx, L, req["k"], req["bmap"], nodes, est["mean"], "linear")
+        mesh = sdd.sdd_subdomain_solve(ctx, req["density"], req["bmap"], L, vert, horiz)["mesh"]
+        torch.cuda.synchronize()
+        st = sdd.walk_stats(est["stats"])
+        assert st["steps"] == out["steps"]
+        assert np.array_equal(mesh.cpu().numpy(), out["mesh"])
+        say(f"  served mesh == estimate + fill + solve, bitwise ({st['steps']} steps)")
