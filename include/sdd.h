@@ -238,6 +238,26 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
                                   sdd_walk_stats* stats, sdd_path_record* per_path, void* workspace,
                                   size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * estimate as sdd_interface_estimate, with the same arguments but no
+ * workspace.  Its scratch (the node sums and a header) is a static device
+ * array of the library, 256 + 96 * sdd_noalloc_max_nodes() bytes (6.3 MB),
+ * which each GPU the library runs on holds until the process ends; the
+ * call allocates nothing.  n_nodes above sdd_noalloc_max_nodes() (65536)
+ * gives SDD_ENOSPC.  Every call on a GPU shares that GPU's array: calls
+ * that overlap on one GPU (other streams, other threads, other contexts)
+ * race and give wrong results; calls in one stream's order are safe.
+ * The first kernel of each call resets the scratch it uses. */
+sdd_status sdd_interface_estimate_noalloc(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap,
+                                          const double* nodes, int64_t n_nodes, int64_t paths_per_node,
+                                          int64_t path_begin, double dt, uint64_t seed, int32_t prec, double t_max,
+                                          int32_t exit_test, double* mean, double* se, double* sums,
+                                          sdd_walk_stats* stats, sdd_path_record* per_path, void* stream);
+
+/* Largest n_nodes sdd_interface_estimate_noalloc accepts. */
+int64_t sdd_noalloc_max_nodes(void);
+
 /* SDD_WARN_CAPPED if the host copy of a walk's stats counts capped paths,
  * SDD_OK otherwise; SDD_EINVAL for NULL. */
 sdd_status sdd_walk_status(const sdd_walk_stats* stats);

@@ -108,6 +108,11 @@ def lib() -> C.CDLL:
     L.sdd_interface_estimate.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), P, I64, I64, I64, D, U64,
                                          I32, D, I32, P, P, P, P, P, P, SZ, P]
     L.sdd_interface_estimate.restype = C.c_int
+    L.sdd_interface_estimate_noalloc.argtypes = [P, C.POINTER(sdd_density), C.POINTER(sdd_bmap), P, I64, I64, I64,
+                                                 D, U64, I32, D, I32, P, P, P, P, P, P]
+    L.sdd_interface_estimate_noalloc.restype = C.c_int
+    L.sdd_noalloc_max_nodes.argtypes = []
+    L.sdd_noalloc_max_nodes.restype = I64
     L.sdd_walk_status.argtypes = [C.POINTER(sdd_walk_stats)]
     L.sdd_walk_status.restype = C.c_int
     L.sdd_layout_node_count.argtypes = [C.POINTER(sdd_layout), I32]
@@ -165,7 +170,7 @@ def lib() -> C.CDLL:
 
 
 EXPORTS = ["sdd_status_string", "sdd_version", "sdd_create", "sdd_destroy", "sdd_workspace_bytes",
-           "sdd_interface_estimate", "sdd_walk_status", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
+           "sdd_interface_estimate", "sdd_walk_status", "sdd_interface_estimate_noalloc", "sdd_noalloc_max_nodes", "sdd_layout_node_count", "sdd_layout_nodes", "sdd_bmap_edge1d_table",
            "sdd_fill_interfaces", "sdd_subdomain_workspace_bytes", "sdd_subdomain_solve", "sdd_server_create",
            "sdd_server_submit", "sdd_server_poll", "sdd_server_wait", "sdd_server_cancel", "sdd_server_clock",
            "sdd_server_destroy", "sdd_quality_workspace_bytes", "sdd_mesh_quality", "sdd_mesh_compare",

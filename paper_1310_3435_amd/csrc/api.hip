@@ -17,6 +17,15 @@ using namespace sdd;
 
 namespace sdd {
 
+// Scratch of sdd_interface_estimate_noalloc: the walk workspace (a 256-byte
+// header and the node sums) for up to kNoAllocMaxNodes nodes, in a
+// file-scope device array that every GPU the library runs on holds until
+// the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress returns for the current device (sdd_ctx::scratch).
+constexpr int64_t kNoAllocMaxNodes = (int64_t)1 << 16;
+constexpr size_t kNoAllocBytes = 256 + (size_t)kNoAllocMaxNodes * sizeof(NodeAcc);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 WalkWorkspace walk_workspace(int64_t n_nodes)
 {
     WalkWorkspace W;
@@ -65,6 +74,17 @@ sdd_status sdd_create(int32_t device, sdd_ctx** out)
     int rate = 0;
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, device) != hipSuccess) rate = 0;
     c->wall_rate_khz = rate;
+    // this device's address of the static scratch array, with the device
+    // current (each GPU holds its own copy)
+    int prev = 0;
+    c->scratch = nullptr;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess ||
+        hipGetSymbolAddress(&c->scratch, HIP_SYMBOL(scratch)) != hipSuccess || !c->scratch) {
+        (void)hipSetDevice(prev);
+        delete c;
+        return SDD_EDEVICE;
+    }
+    (void)hipSetDevice(prev);
     *out = c;
     return SDD_OK;
 }
@@ -180,6 +200,28 @@ sdd_status sdd_interface_estimate(sdd_ctx* ctx, const sdd_density* w, const sdd_
     return run_estimate(ctx, A, (char*)workspace, prec, exit_test, mean, se, sums, stats, per_path,
                         (hipStream_t)stream);
 }
+
+sdd_status sdd_interface_estimate_noalloc(sdd_ctx* ctx, const sdd_density* w, const sdd_bmap* bmap,
+                                          const double* nodes, int64_t n_nodes, int64_t paths_per_node,
+                                          int64_t path_begin, double dt, uint64_t seed, int32_t prec, double t_max,
+                                          int32_t exit_test, double* mean, double* se, double* sums,
+                                          sdd_walk_stats* stats, sdd_path_record* per_path, void* stream)
+{
+    if (!ctx || !ctx->scratch) return SDD_EINVAL;
+    WalkArgs A;
+    sdd_status s = prepare_estimate(w, bmap, nodes, n_nodes, paths_per_node, path_begin, dt, seed, prec, t_max,
+                                    exit_test, mean, ctx->cu_count, A);
+    if (s != SDD_OK) return s;
+    if (n_nodes > kNoAllocMaxNodes || walk_workspace(n_nodes).bytes > kNoAllocBytes) return SDD_ENOSPC;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SDD_EDEVICE;
+    // the header (pool counter, scale, start time) and the node sums are
+    // set by the first kernel of the call, so nothing of an earlier call
+    // carries over
+    return run_estimate(ctx, A, (char*)ctx->scratch, prec, exit_test, mean, se, sums, stats, per_path,
+                        (hipStream_t)stream);
+}
+
+int64_t sdd_noalloc_max_nodes(void) { return kNoAllocMaxNodes; }
 
 sdd_status sdd_walk_status(const sdd_walk_stats* stats)
 {

@@ -13,6 +13,7 @@ struct sdd_ctx {
     int device;
     int cu_count;
     int wall_rate_khz;  // rate of the device wall clock (wall_clock64)
+    void* scratch;      // this device's copy of the library's static scratch array
 };
 
 namespace sdd {
