@@ -238,21 +238,21 @@ inline int walk_kind(const Density& D, int prec)
 
 // Float walks with small steps may compute the next block's Philox beside
 // the current steps (PIPE).  Whether that pays depends on how the compiler
-// schedules each drift and exit test; measured same-box (1521 nodes,
-// steps/s, 4 waves per SIMD, pipelined against plain loop):
+// schedules each drift and exit test; measured same-box (dt = 1e-5, 3
+// waves per SIMD, steps/s, pipelined against plain loop):
 //
-//   dt = 1e-5      gauss   ring    sech^2  sin^2   sum of terms
-//   end of step    -1%     -4%     +5%     +7%     +1.5% (-2% at 8 waves)
-//   bridge         -1.5%   +1.5%   -3%     -4%     +4% (0 at 8 waves)
+//                  Gaussian sum   ring    sech^2   sin^2
+//   end of step    +7%            -0.6%   -3%      +0.2%
+//   bridge         --             +4%     +3%      +5%
 //
-// The sum of terms runs 8 waves per SIMD (launch_walk_kernel), where it no
-// longer pays.  At dt = 1e-4 and 1e-3 it ties or loses for every kind (up
-// to 9%).
+// (the Gaussian-sum figure on a small job of 53 nodes x 2e4 paths).  The
+// general sum of terms takes the plain loop.  At dt = 1e-4 and 1e-3 the
+// pipelined loop tied or lost for every kind (up to 9%).
 template <int KIND, int EXIT>
 static hipError_t launch_f32(const WalkArgs& A, hipStream_t stream)
 {
-    constexpr bool pipe_kind = (EXIT == kExitStep && (KIND == SDD_TERM_SECH2 || KIND == SDD_TERM_SIN2)) ||
-                               (EXIT == kExitBridge && KIND == SDD_TERM_RING);
+    constexpr bool pipe_kind = KIND != kAnyTerms && (EXIT == kExitBridge || (EXIT == kExitStep &&
+                                                     (KIND == kGaussSum || KIND == SDD_TERM_SIN2)));
     if constexpr (pipe_kind) {
         if (A.dt < kLongPathDt) return launch_walk_kernel<float, KIND, EXIT, true>(A, stream);
     }
