@@ -113,14 +113,15 @@ def host_threads() -> int:
         return os.cpu_count() or 1
 
 
-def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int, gpu_mean=None, single_paths: int = 10000):
+def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int, gpu_mean=None, single_paths: int = 10000,
+                 sample_paths: int = 0):
     """The oracle, untuned, on this host's cores: `sample_nodes` evenly spaced
-    nodes of the same workload at its full paths per node, double precision;
-    then one node with `single_paths` paths on one core.  The full
-    workload's oracle time is extrapolated linearly in steps from the
-    all-core rate.  With gpu_mean (the timed run's node estimates: the same
-    counters, so the same paths in float) the sample also gives, node by
-    node, |GPU - oracle| / SE."""
+    nodes of the same workload, `sample_paths` paths each (0: the workload's
+    own), double precision; then one node with `single_paths` paths on one
+    core.  The full workload's oracle time is extrapolated linearly in steps
+    from the all-core rate.  With gpu_mean (the GPU's float estimate of every
+    node over the same first paths: the same counters, so the same paths)
+    the sample also gives, node by node, |GPU - oracle| / SE."""
     import numpy as np
 
     import oracle
@@ -128,8 +129,9 @@ def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int, gpu_mean=None, 
     n = nodes.shape[0]
     idx = (np.arange(sample_nodes) * (n // sample_nodes)).astype(np.int64)
     threads = host_threads()
+    paths = sample_paths or cfg["paths"]
     t0 = time.perf_counter()
-    r = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[idx], cfg["paths"], cfg["dt"], cfg["seed"],
+    r = oracle.interface_estimate(cfg["density"], cfg["bmap"], nodes[idx], paths, cfg["dt"], cfg["seed"],
                                   "fp64", node_ids=idx, nthreads=threads)
     el = time.perf_counter() - t0
     one = idx[sample_nodes // 2: sample_nodes // 2 + 1]
@@ -139,7 +141,7 @@ def cpu_baseline(cfg, nodes, sample_nodes: int, full_steps: int, gpu_mean=None, 
     el1 = time.perf_counter() - t0
     rate = r["steps"] / el
     out = {"value": rate, "unit": "walk steps/s", "cores": threads, "kind": "oracle",
-           "sample": f"{sample_nodes} of {n} nodes (indices i*{n // sample_nodes}), {cfg['paths']} paths/node, "
+           "sample": f"{sample_nodes} of {n} nodes (indices i*{n // sample_nodes}), paths 0..{paths - 1} of each, "
                      f"dt={cfg['dt']}, fp64 walk, {r['steps']} steps in {el:.2f} s",
            "nodes_per_s": sample_nodes / el, "cpu": cpu_model(),
            "single_core": {"value": r1["steps"] / el1, "unit": "walk steps/s",
@@ -582,6 +584,8 @@ def main():
     ap.add_argument("--prec", default=None, help="override the workload's walk precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nodes", type=int, default=8)
+    ap.add_argument("--cpu-sample-paths", type=int, default=25000,
+                    help="paths per sampled node of the oracle baseline (about 15 s on 16 host cores)")
     ap.add_argument("--no-ring", action="store_true", help="skip the ring workload leg")
     ap.add_argument("--ring-oracle-paths", type=int, default=2000,
                     help="paths per node of the ring workload's 64-node oracle subset (0: skip)")
@@ -726,7 +730,6 @@ def main():
         "roofline": roofline(cfg, steps_per_pass, walk_avg_s, traffic_from_profile(args.workload)),
     }
     print(f"[bench] timed: {value:.3e} walk steps/s, {line['ms_per_step']:.1f} ms/pass", file=sys.stderr, flush=True)
-    gpu_mean = est["mean"].cpu().numpy()
     ring = None
     if not args.no_ring:
         print("[bench] ring workload leg", file=sys.stderr, flush=True)
@@ -748,9 +751,12 @@ def main():
         line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst,
                                      bridge_dt=args.serve_bridge_dt, launch_paths=args.serve_launch_paths)
     if not args.no_cpu_baseline:
+        # the same first paths of every node on the GPU, for the per-node comparison
+        sp = min(args.cpu_sample_paths, cfg["paths"])
+        g, _ = timed_estimate(ctx, dens, B, nodes, sp, cfg["dt"], cfg["seed"], cfg["prec"])
         print("[bench] oracle baseline on the host", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(cfg, nodes.cpu().numpy(), args.cpu_sample_nodes, steps_per_pass,
-                                            gpu_mean=gpu_mean)
+                                            gpu_mean=g["mean"].cpu().numpy(), sample_paths=sp)
     print(json.dumps(line), flush=True)
 
 

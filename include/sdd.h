@@ -201,10 +201,11 @@ void sdd_destroy(sdd_ctx* ctx);
  * (ceil(t_max/dt), i.e. t_max in expectation).
  *
  * Node sums are exact: each path's x, y, x^2, y^2 is rounded to a multiple
- * of 2^-F (2^-60 times a power of two bounding the boundary map's image,
- * from its parameters or, for a TABLE map, its table) and added into
- * 64-bit integer limbs, so the sums are independent of the order in which
- * paths finish and the results are bitwise reproducible.  The workspace
+ * of 2^-F (2^-54 times a power of two bounding the boundary map's image,
+ * from its parameters or, for a TABLE map, its table: below a double's
+ * rounding of such values) and added into 64-bit integer limbs, so the
+ * sums are independent of the order in which paths finish and the results
+ * are bitwise reproducible.  The workspace
  * holds these sums (96 bytes per node) and a 256-byte header; the walk
  * keeps each finished path only in on-chip memory until its exit is
  * processed.

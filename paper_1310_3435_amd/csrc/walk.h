@@ -29,10 +29,11 @@ constexpr int64_t kMaxSteps = (int64_t)kInfoSteps;
 enum ExitKind { kExitStep = 0, kExitBridge = 1, kExitLane = 2, kExitExpo = 3 };
 
 // Exact per-node sums.  A path's value v (x, y, x^2 or y^2 at its exit
-// point) is rounded to the integer n = rint(v 2^F) with |n| < 2^61 (F from a
-// bound of the boundary map's image, the same for every path of a job) and
-// added as two limbs, n mod 2^31 and floor(n / 2^31), into 64-bit integer
-// sums: exact for up to 2^32 paths per node.  Integer addition is
+// point) is rounded to the integer n = rint(v 2^F) with |n| <= 2^54 (F from a
+// bound of the boundary map's image, the same for every path of a job); a
+// wave adds the n of up to 64 paths of a node (|sum| <= 2^60) and adds the
+// sum as two limbs, sum mod 2^31 and floor(sum / 2^31), into 64-bit integer
+// sums: exact for up to 2^32 additions per node.  Integer addition is
 // associative, so the sums do not depend on the order in which paths finish
 // and the estimate is reproducible bit for bit under any schedule.
 struct NodeAcc {
@@ -108,7 +109,9 @@ struct ExitEntry {
 };
 
 // Scale of the sums for values bounded by vmax in magnitude: the smallest
-// e with 2^e >= vmax gives F = 60 - e (|v 2^F| <= 2^60) and F2 = 60 - 2e.
+// e with 2^e >= vmax gives F = 54 - e (|v 2^F| <= 2^54) and F2 = 54 - 2e.
+// A value is then rounded to 2^-54 of the bound, below a double's own
+// rounding of values of that size.
 __host__ __device__ inline AccScale scale_for_bound(double vmax)
 {
     int e = 0;
@@ -116,8 +119,8 @@ __host__ __device__ inline AccScale scale_for_bound(double vmax)
     if (e < -200) e = -200;
     if (e > 200) e = 200;
     AccScale S;
-    S.s[0] = ldexp(1.0, 60 - e);
-    S.s[1] = ldexp(1.0, 60 - 2 * e);
+    S.s[0] = ldexp(1.0, 54 - e);
+    S.s[1] = ldexp(1.0, 54 - 2 * e);
     return S;
 }
 

@@ -15,10 +15,10 @@
 // per-wave queue in LDS.  Once the queue holds 64 entries the wave empties
 // it with all lanes at once: each lane projects one path's last step onto
 // the boundary in double (first crossing; the nearest boundary point for a
-// capped path), evaluates the boundary map there (eq. (7a)) and turns the
-// value, its square and the step count into integer contributions to the
-// node's exact sums (walk.h); the wave adds them up per node and one lane
-// per node adds the totals with 64-bit atomics.  The walk keeps no
+// capped path), evaluates the boundary map there (eq. (7a)) and rounds the
+// value and its square to integer contributions to the node's exact sums
+// (walk.h); the wave adds them and the step counts up per node and one
+// lane per node adds the totals with 64-bit atomics.  The walk keeps no
 // double-precision state, the double work runs on full waves, and the sums
 // do not depend on which lane walked which path or when.
 #pragma once
@@ -33,14 +33,6 @@ constexpr int kWavesPerBlock = kWalkBlock / kWave;
 
 // ------------------------------------------------------- exit processing
 
-// Sum of v over the wave (every lane gets it).
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
-{
-#pragma unroll
-    for (int m = kWave / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-    return v;
-}
-
 // A finished path's contribution to its node's sums, kept in the lane
 // between its exit processing and the per-node reduction.
 struct PathValue {
@@ -49,16 +41,11 @@ struct PathValue {
     NodeAcc* acc;      // the node's sums (the reduction key)
 };
 
-// Word q of a path's contribution: q = 2j, 2j+1 the low and high limbs of
-// the j-th of x, y, x^2, y^2 scaled by the job's 2^F (walk.h); q = 8 the
-// step count.
-__device__ __forceinline__ unsigned long long acc_word(const PathValue& v, const AccScale& S, int q)
+// The rounded, scaled j-th of x, y, x^2, y^2 (walk.h): |n| <= 2^54.
+__device__ __forceinline__ long long acc_value(const PathValue& v, const AccScale& S, int j)
 {
-    if (q == 8) return v.steps;
-    const int j = q >> 1;
     const double u = j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.x * v.x : v.y * v.y;
-    const long long n = (long long)rint(u * S.s[j >> 1]);  // |n| <= 2^60
-    return (q & 1) ? (unsigned long long)(n >> 31) : (unsigned long long)(n & 0x7fffffffll);
+    return (long long)rint(u * S.s[j >> 1]);
 }
 
 // Exit point and boundary value of one finished path.  Writes the path's
@@ -98,10 +85,9 @@ __device__ __forceinline__ PathValue finish_path(const WalkJob& J, const ExitEnt
 // A wave's exit queue is a ring of kQueue entries in LDS; it is emptied up
 // to 64 entries at a time, lane i finishing entry head + i.  The entries'
 // contributions are then summed per node across the wave (integer sums:
-// exact, in any order), and one lane per node adds them to the node's sums,
-// so a node's cache line takes one atomic per word per drain instead of one
-// per path.  The words are reduced one at a time, which keeps the drain's
-// registers few.
+// exact, in any order), and one lane per node adds them to the node's sums
+// as limbs, so a node's cache line takes one atomic per word per drain
+// instead of one per path.
 constexpr uint32_t kQueue = 2 * kWave;
 
 template <typename R, bool LANE>
@@ -125,18 +111,33 @@ __device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R
         }
     }
     __builtin_amdgcn_wave_barrier();
+    long long n[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) n[j] = have ? acc_value(v, S, j) : 0ll;
     uint64_t todo = __ballot(have);
     while (todo != 0) {
         const int leader = (int)__builtin_ctzll(todo);
         const unsigned long long key = __shfl((unsigned long long)v.acc, leader, kWave);
         const bool mine = have && (unsigned long long)v.acc == key;
         todo &= ~__ballot(mine);
-        unsigned long long* dst = (unsigned long long*)key;
-#pragma unroll 1
-        for (int q = 0; q < 9; ++q) {
-            const unsigned long long sum = wave_sum(mine ? acc_word(v, S, q) : 0ull);
-            // words 0..7 are lo[0], hi[0], ..., in NodeAcc order lo[4], hi[4], steps
-            if ((int)lane == leader) atomicAdd(dst + (q == 8 ? 8 : (q & 1) * 4 + (q >> 1)), sum);
+        unsigned long long sum[5];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sum[j] = mine ? (unsigned long long)n[j] : 0ull;
+        sum[4] = mine ? v.steps : 0ull;
+#pragma unroll
+        for (int m = kWave / 2; m >= 1; m >>= 1) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) sum[j] += __shfl_xor(sum[j], m, kWave);
+        }
+        if ((int)lane == leader) {
+            NodeAcc* a = (NodeAcc*)key;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long long t = (long long)sum[j];  // |t| <= 2^60
+                atomicAdd(&a->lo[j], (unsigned long long)(t & 0x7fffffffll));
+                atomicAdd(&a->hi[j], (unsigned long long)(t >> 31));
+            }
+            atomicAdd(&a->steps, sum[4]);
         }
     }
 }
@@ -200,8 +201,9 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
     uint32_t qh = 0, qn = 0;  // first entry and entries in the wave's queue (wave-uniform)
     const int lane = threadIdx.x & (kWave - 1);
 
-    // wave-uniform pool: node, next path, end
+    // wave-uniform pool: node, next path, end, and (per-lane jobs) the job
     uint32_t pool_g = 0, pool_p = 0, pool_end = 0, pool_seg = 0;
+    const WalkJob* pool_job = &A.job;
     bool exhausted = false;
     // lane state
     bool live = false;
@@ -250,6 +252,7 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
                 pool_p = S.p_lo + (uint32_t)c * A.pool_paths;
                 pool_end = min(S.p_hi, pool_p + A.pool_paths);
                 pool_seg = (uint32_t)si;
+                if constexpr (LANE) pool_job = S.job;
             }
             const uint32_t avail = pool_end - pool_p;
             const uint32_t want = (uint32_t)__popcll(need);
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
                 g = pool_g;
                 p = pool_p + rank;
                 seg = pool_seg;
-                const WalkJob& J = LANE ? *A.segs[seg].job : A.job;
+                const WalkJob& J = LANE ? *pool_job : A.job;  // the pool's job: a uniform address
                 if constexpr (LANE) {
                     lg = J.gp;
                     dt = J.dt;
