@@ -37,10 +37,10 @@ sys.path.insert(0, ROOT)
 # (FMA = 2, transcendental = 1), the roofline's unit of work: Box-Muller (a
 # log, a sqrt, a sin, a cos, two products), the drift of each density kind
 # (ring: offsets, r^2, rsqrt, exp, rcp and the products; gauss: one
-# exp-term sum; sech^2: exp, two rcp and products; sin^2: sin, cos, rcp and
+# exp-term sum; sech^2: exp, one rcp and products; sin^2: sin, cos, rcp and
 # products), the update (4 FMA) and the exit test.  The peak is MI355X's
 # published FP32 vector rate.
-FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 38, "sin2": 36}
+FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 37, "sin2": 36}
 FP32_PEAK_TFLOPS = 157.3
 # Issue-cycle view, beside the FLOP roofline: SIMD cycles per wave64 step
 # from the algorithm's instruction mix weighted by gfx950's measured issue
@@ -49,11 +49,11 @@ FP32_PEAK_TFLOPS = 157.3
 # v_mad_u64_u32) 4, transcendentals 8).  Per step: a third of a
 # Philox4x32-10 block (20 v_mad_u64_u32 + 20 v_bitop3_b32 = 160 per block),
 # two uniforms (60 per block, 20 a step), Box-Muller 36, the drift (ring 60,
-# gauss 40, sech2 66, sin2 56), the update 16, the exit test 8.  Capacity:
+# gauss 40, sech2 56, sin2 56), the update 16, the exit test 8.  Capacity:
 # 256 CUs x 4 SIMDs x 2.4 GHz.
 _STEP_COMMON = 160 / 3 + 20 + 36 + 16 + 8
 CYCLES_PER_WAVE_STEP = {k: _STEP_COMMON + d for k, d in
-                        {"ring": 60, "gauss": 40, "sech2": 66, "sin2": 56}.items()}
+                        {"ring": 60, "gauss": 40, "sech2": 56, "sin2": 56}.items()}
 ISSUE_PEAK_G = 256 * 4 * 2.4e9 / 1e9  # G SIMD-cycles/s
 # HBM bytes the walk must move per launch: the node table (16 B a node) and
 # the node sums (96 B a node, zeroed then written back); a path reads and
@@ -178,6 +178,7 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
         ids = [srv.submit(r) for r in reqs[:burst]]
         res = [srv.wait(i) for i in ids]
         t_burst = max(r["t_done"] for r in res) - t0
+        burst_steps = sum(r["steps"] for r in res if r["status"] >= 0)
         capacity = burst / t_burst
         rate = load * capacity
         arrivals = workloads.poisson_arrivals(n_requests, rate, seed=seed)
@@ -215,7 +216,8 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
         "arrival_rate_per_s": rate, "capacity_req_per_s": capacity,
         "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
         "mean_latency_ms": float(lat.mean()), "throughput_req_per_s": len(ok) / wall,
-        "walk_steps_per_s": steps / wall, "median_paths_per_node": float(np.median([r["paths_per_node"] for r in ok])),
+        "walk_steps_per_s": steps / wall, "walk_steps": steps, "burst_walk_steps": burst_steps,
+        "median_paths_per_node": float(np.median([r["paths_per_node"] for r in ok])),
         "max_se": float(max(r["max_se"] for r in ok)),
         "capped_paths": int(sum(r["capped"] for r in ok)),
         "stage_ms_median": {k: float(np.median([r[k] for r in ok]))

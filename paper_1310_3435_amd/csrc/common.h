@@ -221,14 +221,17 @@ __device__ inline void drift1_f32(const Density& D, float xi, float eta, float& 
         bx = h * dx;
         by = h * dy;
     } else if (KIND == SDD_TERM_SECH2) {
+        // with q = e^{-2|s|}: sech^2 s = 4q/(1+q)^2 and tanh|s| = (1-q)/(1+q),
+        // so f tanh s / (base + f), f = amp sech^2 s, is
+        // sign(s) 4 amp q (1-q) / ((1+q) (base (1+q)^2 + 4 amp q)): one reciprocal
         const float s = D.fcoef[0] * __builtin_fmaf(D.fnx[0], dx, D.fny[0] * dy);
         const float q = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(s));
-        const float inv = __builtin_amdgcn_rcpf(1.0f + q);
-        const float f = D.famp[0] * 4.0f * q * inv * inv;
-        const float th = copysignf((1.0f - q) * inv, s);
-        const float h = D.fm2c[0] * f * th * __builtin_amdgcn_rcpf(D.fbase + f);
-        bx = h * D.fnx[0];
-        by = h * D.fny[0];
+        const float p = 1.0f + q;
+        const float a4q = (4.0f * D.famp[0]) * q;
+        const float den = p * __builtin_fmaf(D.fbase * p, p, a4q);
+        const float h = copysignf(a4q * (1.0f - q) * __builtin_amdgcn_rcpf(den), s);
+        bx = h * (D.fm2c[0] * D.fnx[0]);
+        by = h * (D.fm2c[0] * D.fny[0]);
     } else {  // SIN2
         const float s = D.fcoef[0] * __builtin_fmaf(D.fnx[0], dx, D.fny[0] * dy);
         float turns = s * kInvTwoPi;

@@ -203,7 +203,9 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
 
     // wave-uniform pool: node, next path, end, and (per-lane jobs) the job
     uint32_t pool_g = 0, pool_p = 0, pool_end = 0, pool_seg = 0;
-    const WalkJob* pool_job = &A.job;
+    // (per-lane jobs only; never the address of the kernel argument, which
+    // would put a copy of the whole argument block in per-lane scratch)
+    const WalkJob* pool_job = nullptr;
     bool exhausted = false;
     // lane state
     bool live = false;
