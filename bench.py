@@ -55,6 +55,13 @@ _STEP_COMMON = 160 / 3 + 20 + 36 + 16 + 8
 CYCLES_PER_WAVE_STEP = {k: _STEP_COMMON + d for k, d in
                         {"ring": 60, "gauss": 40, "sech2": 56, "sin2": 56}.items()}
 ISSUE_PEAK_G = 256 * 4 * 2.4e9 / 1e9  # G SIMD-cycles/s
+# A float sum of n Gaussian bumps (the request server's densities): per term
+# two offsets, a product, two FMAs, the exp, the sum, a product and two
+# gradient FMAs (34 cycles); then one rcp and two products (12).
+
+
+def gauss_sum_cycles(n_terms: int) -> float:
+    return _STEP_COMMON + 34 * n_terms + 12
 # HBM bytes the walk must move per launch: the node table (16 B a node) and
 # the node sums (96 B a node, zeroed then written back); a path reads and
 # writes nothing beyond on-chip memory and the node sums' cache lines.
@@ -226,6 +233,48 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
                   "subdomains, SE 1e-3 per node, float walks, Poisson arrivals, "
                   + (f"bridge exit test at dt {bridge_dt:g}" if bridge_dt > 0 else "end-of-step exit test at dt 1e-4"),
     }
+
+
+def serve_like(ctx, grid: int = 257, sub: int = 8, paths: int = 65536, dt: float = 1e-4):
+    """One request of the serving stream's shape (grid^2, sub x sub
+    subdomains, two Gaussian bumps, end-of-step test) through the server and
+    through sdd_interface_estimate on the same nodes, paths and seed: the
+    same steps (asserted), timed each on its own walk (the server's T_stoc,
+    HIP events around the estimate call), with the issue model of a
+    two-term Gaussian sum beside each rate."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    import workloads
+    terms = [{"kind": "gauss", "amp": 6.0, "coef": 60.0, "cx": 0.4, "cy": 0.55},
+             {"kind": "gauss", "amp": 12.0, "coef": 150.0, "cx": 0.7, "cy": 0.3}]
+    dens = workloads.density(1.0, terms)
+    L = {"nx": grid, "ny": grid, "sx": sub, "sy": sub}
+    k = (grid - 1) // sub - 1
+    req = {"density": dens, "bmap": {"kind": "identity"}, "layout": L, "k": k, "placement": "uniform",
+           "interp": "linear", "dt": dt, "se_target": 0.0, "paths": paths, "seed": 5, "exit_test": "step"}
+    srv = sdd.Server(ctx, hbm_budget_bytes=256 << 20, max_slots=4, max_nodes=8192)
+    try:
+        srv.wait(srv.submit(req))  # loads the kernels
+        r = srv.wait(srv.submit(req))
+    finally:
+        srv.close()
+    nodes = sdd.sdd_layout_nodes(ctx, L, k, "uniform", dens)
+    e, _ = timed_estimate(ctx, dens, {"kind": "identity"}, nodes, r["paths_per_node"], dt, 5, "fp32")
+    e, ms = timed_estimate(ctx, dens, {"kind": "identity"}, nodes, r["paths_per_node"], dt, 5, "fp32", out=e)
+    torch.cuda.synchronize()
+    steps = int(e["stats"].cpu().numpy()[0])
+    assert steps == r["steps"], "the server walked other paths than the estimate call"
+    cyc = gauss_sum_cycles(len(terms))
+    out = {"workload": f"{grid}^2, {sub}x{sub} subdomains, {int(nodes.shape[0])} nodes x {r['paths_per_node']} "
+                       f"paths, two Gaussian bumps, end-of-step test at dt {dt:g}, float walk",
+           "steps": steps, "serve_walk_ms": r["t_stoc_ms"], "estimate_walk_ms": ms,
+           "serve_steps_per_s": steps / (r["t_stoc_ms"] * 1e-3), "estimate_steps_per_s": steps / (ms * 1e-3)}
+    out["serve_over_estimate"] = out["serve_steps_per_s"] / out["estimate_steps_per_s"]
+    out["issue_model"] = {"cycles_per_wave_step": round(cyc, 2), "peak_G_cycles_per_s": ISSUE_PEAK_G,
+                          "serve_frac": out["serve_steps_per_s"] / 64 * cyc / 1e9 / ISSUE_PEAK_G,
+                          "estimate_frac": out["estimate_steps_per_s"] / 64 * cyc / 1e9 / ISSUE_PEAK_G}
+    return out
 
 
 def closed_form_sin2(xi):
@@ -601,6 +650,8 @@ def main():
                     help="paths per serving walk launch (0: the server's default)")
     ap.add_argument("--serve-bridge-dt", type=float, default=1e-3,
                     help="> 0: serving requests use the bridge exit test at this time step (0: end of step, 1e-4)")
+    ap.add_argument("--serve-like", action="store_true",
+                    help="only run one request through the server and through the estimate call (same paths)")
     ap.add_argument("--bias-sweep", action="store_true",
                     help="only run the float/double dt sweep of the closed-form workload")
     ap.add_argument("--sweep-paths", type=int, default=1000000)
@@ -631,6 +682,11 @@ def main():
                           tuple(args.sweep_exit.split(",")))
         print(json.dumps({"bias_sweep": rows, "paths_per_node": args.sweep_paths, "nodes": 64,
                           "workload": "sin2_bias_sweep"}), flush=True)
+        return
+
+    if args.serve_like:
+        import paper_1310_3435_amd as sdd
+        print(json.dumps({"serve_like": serve_like(sdd.Context(0))}), flush=True)
         return
 
     if args.serve_sweep:
@@ -752,6 +808,7 @@ def main():
         print(f"[bench] serving stream of {args.serve_requests} requests", file=sys.stderr, flush=True)
         line["serve"] = serve_stream(ctx, args.serve_requests, args.serve_load, args.serve_burst,
                                      bridge_dt=args.serve_bridge_dt, launch_paths=args.serve_launch_paths)
+        line["serve"]["like_for_like"] = serve_like(ctx)
     if not args.no_cpu_baseline:
         # the same first paths of every node on the GPU, for the per-node comparison
         sp = min(args.cpu_sample_paths, cfg["paths"])

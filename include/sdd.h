@@ -445,7 +445,8 @@ sdd_status sdd_smooth_interfaces(sdd_ctx* ctx, const sdd_layout* L, int32_t span
  * multiple of 1024, where s is the largest sample standard deviation of x
  * or y over its nodes (the paper notes the mean's additivity makes such a
  * stopping rule compatible with the method, Sec. 6).  With se_target <= 0
- * paths_per_node (<= 2^30) is used, rounded up to a multiple of 1024.  The
+ * paths_per_node (<= 2^30) is used, rounded up to a multiple of 1024, and
+ * there is no pilot: every block may go into the first launch.  The
  * node sums are exact and a path's random numbers depend only on (seed,
  * node, path, step), so a request's result is bitwise the same alone or in
  * any mix.

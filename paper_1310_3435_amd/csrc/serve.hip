@@ -259,7 +259,13 @@ void admit(sdd_server* S, std::unique_lock<std::mutex>& lk)
         r->slot = S->free_slots.back();
         S->free_slots.pop_back();
         r->arena_off = off;
-        r->state = PILOT;
+        if (r->spec.se_target > 0.0) {
+            r->state = PILOT;  // one block first: its spread decides the paths
+        } else {
+            // the paths are given: every block is a main block
+            r->nb_total = (uint32_t)((r->spec.paths_per_node + kBlockPaths - 1) / kBlockPaths);
+            r->state = MAIN;
+        }
         r->t_admit = now_s();
         S->active.push_back(r);
         lk.unlock();
@@ -495,35 +501,30 @@ void worker_loop(sdd_server* S)
             Lh.busy = false;
             progress = true;
         }
-        // pilots: copy the sums to the host, then decide the paths (the
-        // pilot block's launch has retired, so its sums are final)
+        // pilots (requests with an SE target): copy the sums to the host,
+        // then decide the paths (the pilot block's launch has retired, so
+        // its sums are final)
         for (Request* r : std::vector<Request*>(S->active)) {
             if (r->state == PILOT && !r->cancelled && r->nb_done >= 1 && !r->pilot_copy) {
-                if (r->spec.se_target > 0.0) {
-                    char* stg = stage(S, r) + stage_acc_off();
-                    lk.unlock();
-                    hipError_t e = hipMemcpyAsync(stg, r->acc, (size_t)r->n_nodes * sizeof(NodeAcc),
-                                                  hipMemcpyDeviceToHost, S->finish_stream);
-                    if (e == hipSuccess) e = hipEventRecord(r->ev_pilot, S->finish_stream);
-                    lk.lock();
-                    if (e != hipSuccess) {
-                        r->status = SDD_EDEVICE;
-                        r->cancelled = true;
-                    }
+                char* stg = stage(S, r) + stage_acc_off();
+                lk.unlock();
+                hipError_t e = hipMemcpyAsync(stg, r->acc, (size_t)r->n_nodes * sizeof(NodeAcc),
+                                              hipMemcpyDeviceToHost, S->finish_stream);
+                if (e == hipSuccess) e = hipEventRecord(r->ev_pilot, S->finish_stream);
+                lk.lock();
+                if (e != hipSuccess) {
+                    r->status = SDD_EDEVICE;
+                    r->cancelled = true;
                 }
                 r->pilot_copy = true;
                 progress = true;
             }
             if (r->state == PILOT && r->pilot_copy && !r->cancelled) {
-                if (r->spec.se_target > 0.0) {
-                    lk.unlock();
-                    const bool ready = hipEventQuery(r->ev_pilot) == hipSuccess;
-                    lk.lock();
-                    if (!ready) continue;
-                    decide_paths(S, r);
-                } else {
-                    r->nb_total = (uint32_t)((r->spec.paths_per_node + kBlockPaths - 1) / kBlockPaths);
-                }
+                lk.unlock();
+                const bool ready = hipEventQuery(r->ev_pilot) == hipSuccess;
+                lk.lock();
+                if (!ready) continue;
+                decide_paths(S, r);
                 r->state = MAIN;
                 progress = true;
             }
