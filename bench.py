@@ -271,6 +271,13 @@ def serve_like(ctx, grid: int = 257, sub: int = 8, paths: int = 65536, dt: float
            "steps": steps, "serve_walk_ms": r["t_stoc_ms"], "estimate_walk_ms": ms,
            "serve_steps_per_s": steps / (r["t_stoc_ms"] * 1e-3), "estimate_steps_per_s": steps / (ms * 1e-3)}
     out["serve_over_estimate"] = out["serve_steps_per_s"] / out["estimate_steps_per_s"]
+    # the plain double path on the same paths: equal standard error
+    sdd.sdd_interface_estimate(ctx, dens, {"kind": "identity"}, nodes, 1024, dt, 5, "fp64")  # loads the kernel
+    e64, ms64 = timed_estimate(ctx, dens, {"kind": "identity"}, nodes, r["paths_per_node"], dt, 5, "fp64")
+    se32, se64 = float(e["se"].median()), float(e64["se"].median())
+    out["fp64_estimate_walk_ms"] = ms64
+    out["median_se"] = {"fp32": se32, "fp64": se64}
+    out["served_fp32_speedup_over_fp64_at_equal_se"] = ms64 / r["t_stoc_ms"]
     out["issue_model"] = {"cycles_per_wave_step": round(cyc, 2), "peak_G_cycles_per_s": ISSUE_PEAK_G,
                           "serve_frac": out["serve_steps_per_s"] / 64 * cyc / 1e9 / ISSUE_PEAK_G,
                           "estimate_frac": out["estimate_steps_per_s"] / 64 * cyc / 1e9 / ISSUE_PEAK_G}
