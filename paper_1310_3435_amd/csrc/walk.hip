@@ -180,7 +180,7 @@ hipError_t launch_finalize(const NodeAcc* acc, const AccScale* scale, int64_t n,
 // time is O(0.1)); launch choices below are measured on either side of it.
 constexpr double kLongPathDt = 2e-5;
 
-template <typename R, int KIND, int EXIT, bool PIPE>
+template <typename R, int KIND, int EXIT, bool PIPE, bool WIDE = false>
 static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
 {
     // A persistent grid of a few waves per SIMD (SDD_WALK_WAVES_PER_SIMD
@@ -190,8 +190,16 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     // idle.  Measured same-box: a single-term kernel runs paths of thousands
     // of steps (dt < 2e-5) 1-4% faster with 3 waves than with 4 (ring,
     // sin^2, sech^2), shorter paths up to 4.5% faster with 4, and loses 2-4%
-    // with 6 or 8; the general sum of terms, whose term loop leaves more
-    // latency to hide, gains 14-21% from 4 to 8.
+    // with 6 or 8.  The general sum of terms, whose term loop leaves more
+    // latency to hide, runs its 64-VGPR instance with 8 waves on short
+    // paths (19% faster than 4 waves of the full-register one at dt = 1e-4,
+    // 5% slower at 1e-5, where it keeps the full-register one).
+    constexpr auto kernel = [] {
+        if constexpr (WIDE)
+            return walk_kernel_wide<R, KIND, EXIT>;
+        else
+            return walk_kernel<R, KIND, EXIT, PIPE, false>;
+    }();
     struct Grid {
         int occ, cus, env;
     };
@@ -201,15 +209,14 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&G.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || G.cus <= 0)
             G.cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&G.occ, walk_kernel<R, KIND, EXIT, PIPE, false>,
-                                                         kWalkBlock, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&G.occ, kernel, kWalkBlock, 0) != hipSuccess ||
             G.occ <= 0)
             G.occ = 2;
         const char* env = getenv("SDD_WALK_WAVES_PER_SIMD");
         if (env && atoi(env) > 0) G.env = atoi(env);
         return G;
     }();
-    int want = KIND == kAnyTerms ? 8 : A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one per SIMD
+    int want = WIDE ? 8 : KIND == kAnyTerms ? 4 : A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one per SIMD
     if (grid.env > 0) want = grid.env;
     const int per_cu_blocks = want < grid.occ ? want : grid.occ;
     // paths to walk, hence waves worth launching
@@ -219,8 +226,7 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     const uint64_t most = (need + kWavesPerBlock - 1) / kWavesPerBlock;
     if ((uint64_t)blocks > most) blocks = (int64_t)most;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((walk_kernel<R, KIND, EXIT, PIPE, false>), dim3((unsigned)blocks), dim3(kWalkBlock), 0,
-                       stream, A);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kWalkBlock), 0, stream, A);
     return hipGetLastError();
 }
 
@@ -246,11 +252,15 @@ inline int walk_kind(const Density& D, int prec)
 //   bridge         --             +4%     +3%      +5%
 //
 // (the Gaussian-sum figure on a small job of 53 nodes x 2e4 paths).  The
-// general sum of terms takes the plain loop.  At dt = 1e-4 and 1e-3 the
-// pipelined loop tied or lost for every kind (up to 9%).
+// general sum of terms takes the plain loop, and on short paths the
+// 64-VGPR instance.  At dt = 1e-4 and 1e-3 the pipelined loop tied or lost
+// for every kind (up to 9%).
 template <int KIND, int EXIT>
 static hipError_t launch_f32(const WalkArgs& A, hipStream_t stream)
 {
+    if constexpr (KIND == kAnyTerms) {
+        if (A.dt >= kLongPathDt) return launch_walk_kernel<float, KIND, EXIT, false, true>(A, stream);
+    }
     constexpr bool pipe_kind = KIND != kAnyTerms && (EXIT == kExitBridge || (EXIT == kExitStep &&
                                                      (KIND == kGaussSum || KIND == SDD_TERM_SIN2)));
     if constexpr (pipe_kind) {

@@ -193,7 +193,7 @@ __device__ __forceinline__ int find_segment(const WalkSeg* segs, int nseg, uint6
 // results, are the same either way.  LANE: per-lane job parameters
 // (request server; float Gaussian sums), else wave-uniform ones in A.
 template <typename R, int KIND, int EXIT, bool PIPE, bool LANE>
-__global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
+__device__ __forceinline__ void walk_body(const WalkArgs& A)
 {
     static_assert(!LANE || (KIND == kGaussSum && EXIT == kExitLane), "the server walks float Gaussian sums");
     __shared__ ExitEntry<R> queues[kWavesPerBlock][kQueue];
@@ -409,6 +409,23 @@ __global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
         qh = (qh + c) & (kQueue - 1);
         qn -= c;
     }
+}
+
+template <typename R, int KIND, int EXIT, bool PIPE, bool LANE>
+__global__ __launch_bounds__(kWalkBlock) void walk_kernel(const WalkArgs A)
+{
+    walk_body<R, KIND, EXIT, PIPE, LANE>(A);
+}
+
+// The same walk held to 64 VGPRs, so that 8 waves fit on a SIMD; what the
+// exit drain's double projection needs beyond that spills to scratch.  The
+// general sum of terms, whose loop over the terms leaves latency that more
+// waves hide, takes it on short paths (see the launch).
+template <typename R, int KIND, int EXIT>
+__global__ __launch_bounds__(kWalkBlock) __attribute__((amdgpu_waves_per_eu(8))) void walk_kernel_wide(
+    const WalkArgs A)
+{
+    walk_body<R, KIND, EXIT, false, false>(A);
 }
 
 }  // namespace sdd
