@@ -69,11 +69,15 @@ WALK_BYTES_PER_NODE = 16 + 2 * 96
 
 
 def kernel_source_hash(src_dir: str = None) -> str:
-    """Hash of the walk kernel's code (comments and layout removed), which
-    ties the committed counter figures to the kernel they were taken on."""
+    """Hash of the walk kernel's code (comments and layout removed) and of
+    the compiler flags (without include paths), which ties the committed
+    counter figures to the kernel they were taken on."""
     import re
+
+    from paper_1310_3435_amd import build
     src_dir = src_dir or os.path.join(ROOT, "paper_1310_3435_amd", "csrc")
     h = hashlib.sha256()
+    h.update(" ".join(f for f in build.FLAGS if not os.path.isabs(f)).encode())
     for f in ("walk.hip", "walk.h", "walk_core.h", "common.h", "rng.h"):
         with open(os.path.join(src_dir, f)) as fh:
             code = fh.read()

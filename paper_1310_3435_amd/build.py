@@ -15,6 +15,10 @@ FLAGS = [
     "-Wall", "-Wno-unused-result",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # loop headers on 64-byte boundaries: the walk's speed then does not
+    # depend on how long the code before its loop happens to be (measured:
+    # +-2-3% between builds otherwise)
+    "-falign-loops=64",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 
