@@ -34,13 +34,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic FP32 floating-point operations per float Euler-Maruyama step
-# (FMA = 2, transcendental = 1), the roofline's unit of work: Box-Muller (a
-# log, a sqrt, a sin, a cos, two products), the drift of each density kind
-# (ring: offsets, r^2, rsqrt, exp, rcp and the products; gauss: one
-# exp-term sum; sech^2: exp, one rcp and products; sin^2: sin, cos, rcp and
-# products), the update (4 FMA) and the exit test.  The peak is MI355X's
+# (FMA = 2, transcendental = 1), the roofline's unit of work, fixed by the
+# method rather than by how the kernel evaluates it: Philox's integer work
+# aside, a step converts two uniforms, makes two Box-Muller normals (log,
+# sqrt, sin, cos and products), evaluates the drift (one Gaussian term: the
+# offsets, r^2, an exp, the gradient products and a reciprocal) and updates
+# both coordinates (4 FMA): 34 flops.  The ring adds a square root and a
+# reciprocal (36), sin^2 takes a sine and a cosine in place of the exp
+# (35), sech^2 an exp and a reciprocal like the Gaussian (34).  The kernel
+# executes fewer (31 for sech^2 after its algebra; the counters report
+# them), which the issue model below accounts.  The peak is MI355X's
 # published FP32 vector rate.
-FP32_FLOPS_PER_STEP = {"ring": 37, "gauss": 30, "sech2": 37, "sin2": 36}
+FP32_FLOPS_PER_STEP = {"ring": 36, "gauss": 34, "sech2": 34, "sin2": 35}
 FP32_PEAK_TFLOPS = 157.3
 # Issue-cycle view, beside the FLOP roofline: SIMD cycles per wave64 step
 # from the algorithm's instruction mix weighted by gfx950's measured issue
@@ -48,20 +53,21 @@ FP32_PEAK_TFLOPS = 157.3
 # ops 2 cycles, three-operand ops (fma, v_bitop3_b32, v_and_or_b32,
 # v_mad_u64_u32) 4, transcendentals 8).  Per step: a third of a
 # Philox4x32-10 block (20 v_mad_u64_u32 + 20 v_bitop3_b32 = 160 per block),
-# two uniforms (60 per block, 20 a step), Box-Muller 36, the drift (ring 60,
-# gauss 40, sech2 56, sin2 56), the update 16, the exit test 8.  Capacity:
-# 256 CUs x 4 SIMDs x 2.4 GHz.
+# two uniforms (60 per block, 20 a step), Box-Muller 36, the drift (ring 56,
+# one Gaussian term 42, sech2 46, sin2 46), the update 16, the exit test 8.
+# Capacity: 256 CUs x 4 SIMDs x 2.4 GHz.
 _STEP_COMMON = 160 / 3 + 20 + 36 + 16 + 8
 CYCLES_PER_WAVE_STEP = {k: _STEP_COMMON + d for k, d in
-                        {"ring": 60, "gauss": 40, "sech2": 56, "sin2": 56}.items()}
+                        {"ring": 56, "gauss": 42, "sech2": 46, "sin2": 46}.items()}
 ISSUE_PEAK_G = 256 * 4 * 2.4e9 / 1e9  # G SIMD-cycles/s
 # A float sum of n Gaussian bumps (the request server's densities): per term
 # two offsets, a product, two FMAs, the exp, the sum, a product and two
-# gradient FMAs (34 cycles); then one rcp and two products (12).
+# gradient FMAs (34 cycles); then one rcp (8; the products by 1/w fuse into
+# the update).
 
 
 def gauss_sum_cycles(n_terms: int) -> float:
-    return _STEP_COMMON + 34 * n_terms + 12
+    return _STEP_COMMON + 34 * n_terms + 8
 # HBM bytes the walk must move per launch: the node table (16 B a node) and
 # the node sums (96 B a node, zeroed then written back); a path reads and
 # writes nothing beyond on-chip memory and the node sums' cache lines.

@@ -35,6 +35,13 @@ struct Density {
     float fcy[SDD_MAX_TERMS], fr0[SDD_MAX_TERMS], fnx[SDD_MAX_TERMS], fny[SDD_MAX_TERMS];
     // la = log2(amp) (amp e^{-c t} = 2^(k2 t + la)), m2c = -2 coef
     float fla[SDD_MAX_TERMS], fm2c[SDD_MAX_TERMS];
+    // single-term sech^2 and sin^2 walks: the argument as a plane
+    // pa xi + pb eta + pc in the unit of its transcendental (sech^2:
+    // 2 log2(e) s, so that e^{-2|s|} = 2^-|.|; sin^2: s / (2 pi) turns), the
+    // Horner constant sd = 2 base + 4 amp (sech^2) and the gradient factors
+    // gx, gy that multiply the term's scalar factor
+    float fpa[SDD_MAX_TERMS], fpb[SDD_MAX_TERMS], fpc[SDD_MAX_TERMS], fsd[SDD_MAX_TERMS];
+    float fgx[SDD_MAX_TERMS], fgy[SDD_MAX_TERMS];
 };
 
 struct Bmap {
@@ -179,10 +186,11 @@ struct GaussParams {
 };
 
 // drift b = grad w / w in float of w = base + sum of Gaussian bumps, the
-// terms taken in order.  The walk of an estimate call (parameters in
-// scalar registers) and the request server's walk (parameters per lane)
-// both evaluate exactly this sequence of operations, so a request walks
-// bit for bit the paths an estimate call walks.
+// terms taken in order; with m2c times the step length (fixed steps) it is
+// b dt.  The walk of an estimate call (parameters in scalar registers) and
+// the request server's walk (parameters per lane) both evaluate exactly
+// this sequence of operations, so a request walks bit for bit the paths an
+// estimate call walks.
 __device__ __forceinline__ void gauss_sum_drift(int n, float base, const float* cx, const float* cy, const float* k2,
                                                 const float* la, const float* m2c, float x, float y, float& bx,
                                                 float& by)
@@ -205,10 +213,14 @@ __device__ __forceinline__ void gauss_sum_drift(int n, float base, const float* 
 }
 
 // drift b = grad w / w in float for a single ring, sech^2 or sin^2 term,
-// written so that the amplitude folds into the exponent and 1/w into one
-// common factor h with b = h (d_xi, d_eta) or b = h (nx, ny).
+// times `scale` (the step length for fixed steps, so that the update's
+// X + b dt is one FMA per coordinate; 1 otherwise), written so that 1/w
+// goes into one common factor h: b = h (d_xi, d_eta) for the ring (its
+// amplitude folded into the exponent), b = h (gx, gy) for sech^2 and
+// sin^2, whose argument is one plane in (xi, eta).  The constants times
+// scale are loop invariants of the walk.
 template <int KIND>
-__device__ inline void drift1_f32(const Density& D, float xi, float eta, float& bx, float& by)
+__device__ inline void drift1_f32(const Density& D, float scale, float xi, float eta, float& bx, float& by)
 {
     const float dx = xi - D.fcx[0], dy = eta - D.fcy[0];
     if (KIND == SDD_TERM_RING) {
@@ -217,40 +229,39 @@ __device__ inline void drift1_f32(const Density& D, float xi, float eta, float& 
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float d = __builtin_fmaf(r2, rinv, -D.fr0[0]);
         const float e = __builtin_amdgcn_exp2f(__builtin_fmaf(D.fk2[0] * d, d, D.fla[0]));
-        const float h = D.fm2c[0] * d * e * rinv * __builtin_amdgcn_rcpf(D.fbase + e);
+        const float h = (D.fm2c[0] * scale) * d * e * rinv * __builtin_amdgcn_rcpf(D.fbase + e);
         bx = h * dx;
         by = h * dy;
     } else if (KIND == SDD_TERM_SECH2) {
         // with q = e^{-2|s|}: sech^2 s = 4q/(1+q)^2 and tanh|s| = (1-q)/(1+q),
         // so f tanh s / (base + f), f = amp sech^2 s, is
-        // sign(s) 4 amp q (1-q) / ((1+q) (base (1+q)^2 + 4 amp q)): one reciprocal
-        const float s = D.fcoef[0] * __builtin_fmaf(D.fnx[0], dx, D.fny[0] * dy);
-        const float q = __builtin_amdgcn_exp2f(-2.0f * kLog2e * fabsf(s));
-        const float p = 1.0f + q;
-        const float a4q = (4.0f * D.famp[0]) * q;
-        const float den = p * __builtin_fmaf(D.fbase * p, p, a4q);
-        const float h = copysignf(a4q * (1.0f - q) * __builtin_amdgcn_rcpf(den), s);
-        bx = h * (D.fm2c[0] * D.fnx[0]);
-        by = h * (D.fm2c[0] * D.fny[0]);
+        //   sign(s) 4 amp q (1-q) / ((1+q) (base (1+q)^2 + 4 amp q)),
+        // with base (1+q)^2 + 4 amp q = base + q (2 base + 4 amp + base q):
+        // one reciprocal, and 4 amp m2c n in the gradient factors
+        const float s2 = __builtin_fmaf(D.fpa[0], xi, __builtin_fmaf(D.fpb[0], eta, D.fpc[0]));
+        const float q = __builtin_amdgcn_exp2f(-fabsf(s2));
+        const float dq = __builtin_fmaf(q, __builtin_fmaf(D.fbase, q, D.fsd[0]), D.fbase);
+        const float den = __builtin_fmaf(q, dq, dq);
+        const float h = copysignf(__builtin_fmaf(-q, q, q) * __builtin_amdgcn_rcpf(den), s2);
+        bx = h * (D.fgx[0] * scale);
+        by = h * (D.fgy[0] * scale);
     } else {  // SIN2
-        const float s = D.fcoef[0] * __builtin_fmaf(D.fnx[0], dx, D.fny[0] * dy);
-        float turns = s * kInvTwoPi;
+        float turns = __builtin_fmaf(D.fpa[0], xi, __builtin_fmaf(D.fpb[0], eta, D.fpc[0]));
         turns = turns - floorf(turns);
         const float sn = __builtin_amdgcn_sinf(turns);
         const float cs = __builtin_amdgcn_cosf(turns);
-        const float f = D.famp[0] * sn * sn;
-        const float h = -D.fm2c[0] * D.famp[0] * sn * cs * __builtin_amdgcn_rcpf(D.fbase + f);
-        bx = h * D.fnx[0];
-        by = h * D.fny[0];
+        const float h = sn * cs * __builtin_amdgcn_rcpf(__builtin_fmaf(D.famp[0] * sn, sn, D.fbase));
+        bx = h * (D.fgx[0] * scale);
+        by = h * (D.fgy[0] * scale);
     }
 }
 
-// drift b = grad w / w in float.
+// drift b = grad w / w in float, times scale (see drift1_f32).
 template <int KIND = kAnyTerms>
-__device__ inline void drift_f32(const Density& D, float xi, float eta, float& bx, float& by)
+__device__ inline void drift_f32(const Density& D, float scale, float xi, float eta, float& bx, float& by)
 {
     if (KIND >= 0) {
-        drift1_f32<KIND>(D, xi, eta, bx, by);
+        drift1_f32<KIND>(D, scale, xi, eta, bx, by);
         return;
     }
     float W = D.fbase, Gx = 0.0f, Gy = 0.0f;
@@ -265,7 +276,7 @@ __device__ inline void drift_f32(const Density& D, float xi, float eta, float& b
             }
         }
     }
-    const float iw = __builtin_amdgcn_rcpf(W);
+    const float iw = __builtin_amdgcn_rcpf(W) * scale;
     bx = Gx * iw;
     by = Gy * iw;
 }

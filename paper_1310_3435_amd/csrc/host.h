@@ -84,6 +84,24 @@ inline Density to_device(const sdd_density* w)
         D.fr0[t] = (float)T.r0;
         D.fnx[t] = (float)T.nx;
         D.fny[t] = (float)T.ny;
+        // the argument's plane and the gradient factors (common.h, drift1_f32)
+        const double off = -(T.nx * T.cx + T.ny * T.cy);
+        if (T.kind == SDD_TERM_SECH2) {
+            const double k = 2.0 * 1.4426950408889634073599246810019 * T.coef;  // 2 log2(e) coef
+            D.fpa[t] = (float)(k * T.nx);
+            D.fpb[t] = (float)(k * T.ny);
+            D.fpc[t] = (float)(k * off);
+            D.fsd[t] = (float)(2.0 * w->base + 4.0 * T.amp);
+            D.fgx[t] = (float)(-8.0 * T.amp * T.coef * T.nx);  // 4 amp m2c n
+            D.fgy[t] = (float)(-8.0 * T.amp * T.coef * T.ny);
+        } else if (T.kind == SDD_TERM_SIN2) {
+            const double k = T.coef / 6.283185307179586476925286766559;  // turns
+            D.fpa[t] = (float)(k * T.nx);
+            D.fpb[t] = (float)(k * T.ny);
+            D.fpc[t] = (float)(k * off);
+            D.fgx[t] = (float)(2.0 * T.amp * T.coef * T.nx);  // -m2c amp n
+            D.fgy[t] = (float)(2.0 * T.amp * T.coef * T.ny);
+        }
     }
     return D;
 }

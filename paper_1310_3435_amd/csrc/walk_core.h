@@ -23,6 +23,8 @@
 // do not depend on which lane walked which path or when.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "rng.h"
 #include "walk.h"
@@ -144,18 +146,25 @@ __device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R
 
 // ------------------------------------------------------------ the walk
 
+// The drift times `scale`: the float walk with fixed steps takes b dt
+// (scale = dt: the constants times dt are loop invariants, and the update
+// X + b dt becomes one FMA per coordinate), exponential steps b (scale 1).
+// The double walk takes b.
 template <int KIND>
-__device__ __forceinline__ void drift(const WalkArgs& A, float x, float y, float& bx, float& by)
+__device__ __forceinline__ void drift(const WalkArgs& A, float scale, float x, float y, float& bx, float& by)
 {
     if constexpr (KIND == kGaussSum) {
         const GaussParams& G = A.job.gp;
-        gauss_sum_drift(G.n_terms, G.base, G.cx, G.cy, G.k2, G.la, G.m2c, x, y, bx, by);
+        float m2c[SDD_MAX_TERMS];
+#pragma unroll
+        for (int q = 0; q < SDD_MAX_TERMS; ++q) m2c[q] = G.m2c[q] * scale;
+        gauss_sum_drift(G.n_terms, G.base, G.cx, G.cy, G.k2, G.la, m2c, x, y, bx, by);
     } else {
-        drift_f32<KIND>(A.dens, x, y, bx, by);
+        drift_f32<KIND>(A.dens, scale, x, y, bx, by);
     }
 }
 template <int KIND>
-__device__ __forceinline__ void drift(const WalkArgs& A, double x, double y, double& bx, double& by)
+__device__ __forceinline__ void drift(const WalkArgs& A, double, double x, double y, double& bx, double& by)
 {
     drift_f64<KIND>(A.dens, x, y, bx, by);
 }
@@ -220,6 +229,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
     uint32_t key0 = A.job.key0, key1 = A.job.key1;
     bool lbridge = false;
     GaussParams lg;
+    // Euler-Maruyama step x + b dt + s z: float walks with fixed steps get
+    // b dt from the drift (scale dt, one FMA fewer per coordinate), others b
+    constexpr bool kDriftDt = std::is_same<R, float>::value && EXIT != kExitExpo;
+    const float dscale = kDriftDt ? (float)A.dt : 1.0f;
+    auto euler = [](R x, R b, R d, R s, R z) { return kDriftDt ? fmar(s, z, x + b) : fmar(s, z, fmar(b, d, x)); };
     if constexpr (LANE) {
         lg.n_terms = 0;
         lg.base = 1.0f;
@@ -269,6 +283,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
                 if constexpr (LANE) {
                     lg = J.gp;
                     dt = J.dt;
+                    // the server's steps are fixed: its drift is b dt (see drift)
+#pragma unroll
+                    for (int q = 0; q < SDD_MAX_TERMS; ++q) lg.m2c[q] *= dt;
                     sd = J.noise;
                     bc = J.bridge_c;
                     lbridge = J.exit_test == SDD_EXIT_BRIDGE;
@@ -326,21 +343,21 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
         // step 3m
         normals(field_hi(r.x, R(0)), field_hi(r.y, R(0)), z0, z1);
         if constexpr (LANE) gauss_sum_drift(lg.n_terms, lg.base, lg.cx, lg.cy, lg.k2, lg.la, lg.m2c, X, Y, bx, by);
-        else drift<KIND>(A, X, Y, bx, by);
-        const R XA = fmar(sA, z0, fmar(bx, dA, X));
-        const R YA = fmar(sA, z1, fmar(by, dA, Y));
+        else drift<KIND>(A, dscale, X, Y, bx, by);
+        const R XA = euler(X, bx, dA, sA, z0);
+        const R YA = euler(Y, by, dA, sA, z1);
         // step 3m+1
         normals(field_hi(r.z, R(0)), field_hi(r.w, R(0)), z0, z1);
         if constexpr (LANE) gauss_sum_drift(lg.n_terms, lg.base, lg.cx, lg.cy, lg.k2, lg.la, lg.m2c, XA, YA, bx, by);
-        else drift<KIND>(A, XA, YA, bx, by);
-        const R XB = fmar(sB, z0, fmar(bx, dB, XA));
-        const R YB = fmar(sB, z1, fmar(by, dB, YA));
+        else drift<KIND>(A, dscale, XA, YA, bx, by);
+        const R XB = euler(XA, bx, dB, sB, z0);
+        const R YB = euler(YA, by, dB, sB, z1);
         // step 3m+2
         normals(field_lo(r.x, r.y, R(0)), field_lo(r.z, r.w, R(0)), z0, z1);
         if constexpr (LANE) gauss_sum_drift(lg.n_terms, lg.base, lg.cx, lg.cy, lg.k2, lg.la, lg.m2c, XB, YB, bx, by);
-        else drift<KIND>(A, XB, YB, bx, by);
-        const R XC = fmar(sC, z0, fmar(bx, dC, XB));
-        const R YC = fmar(sC, z1, fmar(by, dC, YB));
+        else drift<KIND>(A, dscale, XB, YB, bx, by);
+        const R XC = euler(XB, bx, dC, sC, z0);
+        const R YC = euler(YB, by, dC, sC, z1);
 
         // the step cap is a whole number of blocks, so it can only fall
         // after step 3m+2

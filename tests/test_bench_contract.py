@@ -34,7 +34,7 @@ def test_source_hash_ignores_comments(tmp_path):
 def test_cycle_model_adds_up():
     import bench
     common = 160 / 3 + 20 + 36 + 16 + 8
-    for kind, drift in {"ring": 60, "gauss": 40, "sech2": 56, "sin2": 56}.items():
+    for kind, drift in {"ring": 56, "gauss": 42, "sech2": 46, "sin2": 46}.items():
         assert bench.CYCLES_PER_WAVE_STEP[kind] == pytest.approx(common + drift)
     assert bench.ISSUE_PEAK_G == pytest.approx(256 * 4 * 2.4)
 
