@@ -378,12 +378,4 @@ __device__ inline int nearest_side(double px, double py, double& ex, double& ey)
     return side;
 }
 
-// Neumaier compensated accumulation.
-__device__ inline void nadd(double& s, double& c, double v)
-{
-    const double t = s + v;
-    c += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
-    s = t;
-}
-
 }  // namespace sdd
