@@ -1,12 +1,15 @@
 """GPU tests of the request server (continuous batching).
 
 * a request's mesh is bitwise the same alone and in a mix of other requests
-  (paths depend only on their counters; blocks reduce in a fixed order);
+  (paths depend only on their counters; node sums are exact integers);
 * a served request agrees with the oracle's pipeline under common random
   numbers (within 3 standard errors of the double-precision walk);
 * admission by device memory: a budget that holds one request runs the
   stream one at a time, first come first served;
-* cancellation and shutdown with work in flight end cleanly.
+* cancellation and shutdown with work in flight end cleanly;
+* bridge and capped requests against the oracle, and served requests (with
+  an SE target, or with a fixed path count and no pilot) bitwise equal to
+  the estimate call followed by the fill and the solves.
 """
 import numpy as np
 import pytest
@@ -234,3 +237,35 @@ def test_served_request_equals_the_estimate_call_bitwise(ctx):
         assert st["steps"] == out["steps"]
         assert np.array_equal(mesh.cpu().numpy(), out["mesh"])
         say(f"  served mesh == estimate + fill + solve, bitwise ({st['steps']} steps)")
+
+
+def test_fixed_path_request_equals_the_estimate_call_bitwise(ctx):
+    """A request that gives its path count (no SE target) has no pilot: all
+    of its blocks may go into the first launch.  Its paths per node are the
+    count rounded up to whole blocks of 1024, and, alone or behind other
+    requests, it walks exactly the paths of the estimate call."""
+    import torch
+
+    import paper_1310_3435_amd as sdd
+    req = small_request(seed=23, n=65, s=2, paths=5000, se=0.0)
+    srv = sdd.Server(ctx, hbm_budget_bytes=256 << 20, max_slots=8)
+    try:
+        say("serve: a fixed-path request alone, then behind six others")
+        alone = srv.wait(srv.submit(req))
+        others = [srv.submit(r) for r in W.serving_requests(6, master_seed=4, grids=(33, 65), splits=(2, 4))]
+        mixed = srv.wait(srv.submit(req))
+        rest = [srv.wait(i) for i in others]
+    finally:
+        srv.close()
+    assert alone["status"] == mixed["status"] == 0 and all(r["status"] >= 0 for r in rest)
+    assert alone["paths_per_node"] == mixed["paths_per_node"] == 5120
+    assert np.array_equal(alone["mesh"], mixed["mesh"]) and alone["steps"] == mixed["steps"]
+    L = req["layout"]
+    nodes = sdd.sdd_layout_nodes(ctx, L, req["k"], "uniform", req["density"])
+    est = sdd.sdd_interface_estimate(ctx, req["density"], req["bmap"], nodes, 5120, req["dt"], req["seed"], "fp32")
+    vert, horiz = sdd.sdd_fill_interfaces(ctx, L, req["k"], req["bmap"], nodes, est["mean"], "linear")
+    mesh = sdd.sdd_subdomain_solve(ctx, req["density"], req["bmap"], L, vert, horiz)["mesh"]
+    torch.cuda.synchronize()
+    assert sdd.walk_stats(est["stats"])["steps"] == alone["steps"]
+    assert np.array_equal(mesh.cpu().numpy(), alone["mesh"])
+    say(f"  5000 -> 5120 paths per node, alone == in a mix == estimate + fill + solve, bitwise")
