@@ -92,6 +92,15 @@ __device__ __forceinline__ PathValue finish_path(const WalkJob& J, const ExitEnt
 // instead of one per path.
 constexpr uint32_t kQueue = 2 * kWave;
 
+// Lane `lane`'s 64-bit value in scalar registers.  The builtin returns a
+// signed 32-bit int: each half is taken unsigned before it is widened.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
 template <typename R, bool LANE>
 __device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R>* queue, uint32_t head,
                                             uint32_t count)
@@ -119,9 +128,11 @@ __device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R
     uint64_t todo = __ballot(have);
     while (todo != 0) {
         const int leader = (int)__builtin_ctzll(todo);
-        const unsigned long long key = __shfl((unsigned long long)v.acc, leader, kWave);
-        const bool mine = have && (unsigned long long)v.acc == key;
-        todo &= ~__ballot(mine);
+        const unsigned long long acc = (unsigned long long)v.acc;
+        const unsigned long long key = uniform_u64(acc, leader);
+        const bool mine = have && acc == key;
+        // (the leader's bit goes in any case: every pass retires a lane)
+        todo &= ~(__ballot(mine) | (1ull << leader));
         unsigned long long sum[5];
 #pragma unroll
         for (int j = 0; j < 4; ++j) sum[j] = mine ? (unsigned long long)n[j] : 0ull;
@@ -184,13 +195,23 @@ __device__ __forceinline__ double expo_noise(double tau) { return sqrt(2.0 * tau
 __device__ __forceinline__ float expo_bridge(float tau) { return -kLog2e * __builtin_amdgcn_rcpf(tau); }
 __device__ __forceinline__ double expo_bridge(double tau) { return tau; }
 
+// Wave-uniform reads of data the walk never writes (segments, jobs, node
+// coordinates) go through the constant address space, so that they are
+// scalar loads through the scalar cache rather than a load per lane.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* uniform_ptr(const T* p)
+{
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
 // Segment of pool q (server): the last segment with pool_base <= q.
 __device__ __forceinline__ int find_segment(const WalkSeg* segs, int nseg, uint64_t q)
 {
+    const auto* cs = uniform_ptr(segs);
     int lo = 0, hi = nseg;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (segs[mid].pool_base <= q) lo = mid; else hi = mid;
+        if (cs[mid].pool_base <= q) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -212,6 +233,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
 
     // wave-uniform pool: node, next path, end, and (per-lane jobs) the job
     uint32_t pool_g = 0, pool_p = 0, pool_end = 0, pool_seg = 0;
+    double pool_x = 0.0, pool_y = 0.0;  // per-lane jobs: the pool's node (scalar loads)
     // (per-lane jobs only; never the address of the kernel argument, which
     // would put a copy of the whole argument block in per-lane scratch)
     const WalkJob* pool_job = nullptr;
@@ -248,17 +270,25 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
             if (pool_p == pool_end) {
                 unsigned long long q = 0;
                 if (lane == 0) q = atomicAdd(A.counter, 1ull);
-                q = __shfl(q, 0, kWave);
-                // wave-uniform: keep it in scalar registers
-                q = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(q >> 32)) << 32) |
-                    __builtin_amdgcn_readfirstlane((uint32_t)q);
+                q = uniform_u64(q, 0);  // lane 0's ticket, in scalar registers
                 if (q >= A.total_pools) {
                     exhausted = true;
                     break;
                 }
                 int si = 0;
-                if constexpr (LANE) si = find_segment(A.segs, A.nseg, q);
-                const WalkSeg& S = LANE ? A.segs[si] : A.seg;
+                WalkSeg S;
+                if constexpr (LANE) {
+                    si = find_segment(A.segs, A.nseg, q);
+                    const auto* cs = uniform_ptr(A.segs) + si;
+                    S.pool_base = cs->pool_base;
+                    S.job = cs->job;
+                    S.n_nodes = cs->n_nodes;
+                    S.p_lo = cs->p_lo;
+                    S.p_hi = cs->p_hi;
+                    pool_job = S.job;
+                } else {
+                    S = A.seg;
+                }
                 // pools go round the nodes (pool j of node g is local pool
                 // j n + g), so that waves working at the same time add into
                 // different nodes' sums
@@ -268,7 +298,11 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
                 pool_p = S.p_lo + (uint32_t)c * A.pool_paths;
                 pool_end = min(S.p_hi, pool_p + A.pool_paths);
                 pool_seg = (uint32_t)si;
-                if constexpr (LANE) pool_job = S.job;
+                if constexpr (LANE) {
+                    const double* nodes = uniform_ptr(pool_job)->nodes;
+                    pool_x = uniform_ptr(nodes)[2 * (size_t)pool_g];
+                    pool_y = uniform_ptr(nodes)[2 * (size_t)pool_g + 1];
+                }
             }
             const uint32_t avail = pool_end - pool_p;
             const uint32_t want = (uint32_t)__popcll(need);
@@ -281,20 +315,33 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
                 seg = pool_seg;
                 const WalkJob& J = LANE ? *pool_job : A.job;  // the pool's job: a uniform address
                 if constexpr (LANE) {
-                    lg = J.gp;
-                    dt = J.dt;
-                    // the server's steps are fixed: its drift is b dt (see drift)
+                    const auto* cj = uniform_ptr(pool_job);
+                    lg.n_terms = cj->gp.n_terms;
+                    lg.base = cj->gp.base;
+                    dt = cj->dt;
 #pragma unroll
-                    for (int q = 0; q < SDD_MAX_TERMS; ++q) lg.m2c[q] *= dt;
-                    sd = J.noise;
-                    bc = J.bridge_c;
-                    lbridge = J.exit_test == SDD_EXIT_BRIDGE;
-                    mmax = J.kblocks;
-                    key0 = J.key0;
-                    key1 = J.key1;
+                    for (int q = 0; q < SDD_MAX_TERMS; ++q) {
+                        lg.cx[q] = cj->gp.cx[q];
+                        lg.cy[q] = cj->gp.cy[q];
+                        lg.k2[q] = cj->gp.k2[q];
+                        lg.la[q] = cj->gp.la[q];
+                        // the server's steps are fixed: its drift is b dt (see drift)
+                        lg.m2c[q] = cj->gp.m2c[q] * dt;
+                    }
+                    sd = cj->noise;
+                    bc = cj->bridge_c;
+                    lbridge = cj->exit_test == SDD_EXIT_BRIDGE;
+                    mmax = cj->kblocks;
+                    key0 = cj->key0;
+                    key1 = cj->key1;
+                    pc = cj->path0 + p;
+                } else {
+                    pc = A.job.path0 + p;
                 }
-                pc = J.path0 + p;
-                const double nx0 = J.nodes[2 * (size_t)g], ny0 = J.nodes[2 * (size_t)g + 1];
+                // (an estimate call's kernel keeps its scalar registers for
+                // the wave-uniform density: per-lane loads of the node)
+                const double nx0 = LANE ? pool_x : A.job.nodes[2 * (size_t)g];
+                const double ny0 = LANE ? pool_y : A.job.nodes[2 * (size_t)g + 1];
                 if (nx0 > 0.0 && nx0 < 1.0 && ny0 > 0.0 && ny0 < 1.0) {
                     X = (R)nx0;
                     Y = (R)ny0;
