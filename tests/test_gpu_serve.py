@@ -130,6 +130,8 @@ def test_rejected_requests(ctx):
                                           "r0": 0.2}])
         with pytest.raises(sdd.SddError, match="unsupported"):
             srv.submit(ring)
+        with pytest.raises(sdd.SddError, match="unsupported"):   # exponential stepping: estimate calls only
+            srv.submit(dict(small_request(), exit_test="expo"))
         with pytest.raises(sdd.SddError, match="invalid"):
             srv.submit(small_request(n=129, s=2))     # more points than max_points
         with pytest.raises(sdd.SddError, match="invalid"):
