@@ -17,12 +17,14 @@
 // the boundary in double (first crossing; the nearest boundary point for a
 // capped path), evaluates the boundary map there (eq. (7a)) and rounds the
 // value and its square to integer contributions to the node's exact sums
-// (walk.h); the wave adds them and the step counts up per node and one
-// lane per node adds the totals with 64-bit atomics.  The walk keeps no
-// double-precision state, the double work runs on full waves, and the sums
-// do not depend on which lane walked which path or when.
+// (walk.h); the wave adds them and the step counts up per node into one of
+// two node slots it keeps in LDS, and a slot goes to the node's sums in
+// device memory with 64-bit atomics when the wave moves on to other nodes.
+// The walk keeps no double-precision state, the double work runs on full
+// waves, and the sums do not depend on which lane walked which path or when.
 #pragma once
 
+#include <cstddef>
 #include <type_traits>
 
 #include "common.h"
@@ -87,10 +89,70 @@ __device__ __forceinline__ PathValue finish_path(const WalkJob& J, const ExitEnt
 // A wave's exit queue is a ring of kQueue entries in LDS; it is emptied up
 // to 64 entries at a time, lane i finishing entry head + i.  The entries'
 // contributions are then summed per node across the wave (integer sums:
-// exact, in any order), and one lane per node adds them to the node's sums
-// as limbs, so a node's cache line takes one atomic per word per drain
-// instead of one per path.
+// exact, in any order), and one lane per node adds them as limbs to one of
+// the wave's kSlots node slots in LDS.  A slot goes to the node's sums in
+// device memory (nine atomics) only when another node needs it (the least
+// recently used slot goes) and at the end of the walk, so a node whose pool
+// spans several drains costs nine atomics per pool instead of nine per
+// drain.  Paths of a pool finish long after the pool's last path started
+// (exit times have an exponential tail), so a wave has two or three nodes
+// in flight; four slots keep them all.  The limb totals, and with them the
+// results, are the same either way.
 constexpr uint32_t kQueue = 2 * kWave;
+
+// A wave's node slots: the node's sums address (0: empty) and the limbs
+// lo[4], hi[4] and the step count, as in NodeAcc, and when each was last
+// used.  Different lanes of the wave touch them in turn (the leader of each
+// node), so every access is a wave-scope atomic: in order, and never kept
+// in a lane's registers.
+constexpr int kSlots = 4;
+struct NodeSlots {
+    unsigned long long key[kSlots];
+    unsigned long long w[kSlots][9];
+    uint32_t stamp[kSlots];
+    uint32_t tick;
+};
+
+// The calling wave's slots (an address the compiler recomputes where it
+// needs it rather than keeping it in a register across the walk).
+__device__ __forceinline__ NodeSlots& wave_slots()
+{
+    __shared__ NodeSlots slots[kWavesPerBlock];
+    return slots[threadIdx.x / kWave];
+}
+
+__device__ __forceinline__ unsigned long long slot_load(const unsigned long long* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void slot_store(unsigned long long* p, unsigned long long v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ uint32_t stamp_load(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void stamp_store(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+static_assert(offsetof(NodeAcc, hi) == offsetof(NodeAcc, lo) + 32 && offsetof(NodeAcc, steps) == offsetof(NodeAcc, lo) + 64,
+              "a node slot's nine words follow NodeAcc's lo, hi, steps");
+
+// Add slot s to its node's sums in device memory and empty it.
+__device__ __forceinline__ void flush_slot(NodeSlots& c, uint32_t s)
+{
+    NodeAcc* a = (NodeAcc*)slot_load(&c.key[s]);
+    // lo[4], hi[4], steps: the slot's words in NodeAcc's order
+    unsigned long long* dst = &a->lo[0];
+    for (int j = 0; j < 9; ++j) {
+        atomicAdd(dst + j, slot_load(&c.w[s][j]));
+        slot_store(&c.w[s][j], 0ull);
+    }
+    slot_store(&c.key[s], 0ull);
+}
 
 // Lane `lane`'s 64-bit value in scalar registers.  The builtin returns a
 // signed 32-bit int: each half is taken unsigned before it is widened.
@@ -133,24 +195,66 @@ __device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R
         const bool mine = have && acc == key;
         // (the leader's bit goes in any case: every pass retires a lane)
         todo &= ~(__ballot(mine) | (1ull << leader));
-        unsigned long long sum[5];
+        const uint32_t cnt = (uint32_t)__popcll(__ballot(mine));
+        // The node's lanes' n and step counts summed across the wave in 32-bit
+        // words that cannot carry over 64 lanes, so that no add needs the
+        // carry of another and the shuffles of a round all go out together:
+        // n = l0 + l1 2^26 + l2 2^52 with l0, l1 26-bit fields and |l2| <= 4
+        // (kept as l2 + 4 in 10-bit fields), the step count as its low 26
+        // bits and the rest.
+        uint32_t w[11];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) sum[j] = mine ? (unsigned long long)n[j] : 0ull;
-        sum[4] = mine ? v.steps : 0ull;
+        for (int j = 0; j < 4; ++j) {
+            w[2 * j] = mine ? (uint32_t)(n[j] & 0x3ffffffll) : 0u;
+            w[2 * j + 1] = mine ? (uint32_t)((n[j] >> 26) & 0x3ffffffll) : 0u;
+        }
+        w[8] = mine ? (v.steps & 0x3ffffffu) : 0u;
+        w[9] = mine ? ((uint32_t)((n[0] >> 52) + 4) | (uint32_t)((n[1] >> 52) + 4) << 10 |
+                       (uint32_t)((n[2] >> 52) + 4) << 20)
+                    : 0u;
+        w[10] = mine ? ((uint32_t)((n[3] >> 52) + 4) | (v.steps >> 26) << 10) : 0u;
 #pragma unroll
         for (int m = kWave / 2; m >= 1; m >>= 1) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) sum[j] += __shfl_xor(sum[j], m, kWave);
+            for (int j = 0; j < 11; ++j) w[j] += (uint32_t)__shfl_xor((int)w[j], m, kWave);
         }
         if ((int)lane == leader) {
-            NodeAcc* a = (NodeAcc*)key;
+            NodeSlots& slots = wave_slots();
+            uint32_t s = kSlots;
+#pragma unroll
+            for (int i = 0; i < kSlots; ++i)
+                if (slot_load(&slots.key[i]) == key) s = (uint32_t)i;
+            const uint32_t tick = stamp_load(&slots.tick) + 1u;
+            if (s == kSlots) {
+                // an empty slot, else the least recently used one
+                uint32_t oldest = 0xffffffffu;
+                s = 0u;
+#pragma unroll
+                for (int i = 0; i < kSlots; ++i) {
+                    const uint32_t t = slot_load(&slots.key[i]) == 0ull ? 0u : stamp_load(&slots.stamp[i]);
+                    if (t < oldest) {
+                        oldest = t;
+                        s = (uint32_t)i;
+                    }
+                }
+                if (slot_load(&slots.key[s]) != 0ull) flush_slot(slots, s);
+                slot_store(&slots.key[s], key);
+            }
+            stamp_store(&slots.stamp[s], tick);
+            stamp_store(&slots.tick, tick);
+            const uint32_t h[4] = { w[9] & 0x3ffu, (w[9] >> 10) & 0x3ffu, (w[9] >> 20) & 0x3ffu, w[10] & 0x3ffu };
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const long long t = (long long)sum[j];  // |t| <= 2^60
-                atomicAdd(&a->lo[j], (unsigned long long)(t & 0x7fffffffll));
-                atomicAdd(&a->hi[j], (unsigned long long)(t >> 31));
+                // the node's sum of n over these lanes, |t| <= 2^60
+                const long long t = (long long)w[2 * j] + ((long long)w[2 * j + 1] << 26) +
+                                    ((long long)((int)h[j] - 4 * (int)cnt) << 52);
+                __hip_atomic_fetch_add(&slots.w[s][j], (unsigned long long)(t & 0x7fffffffll), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+                __hip_atomic_fetch_add(&slots.w[s][4 + j], (unsigned long long)(t >> 31), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
             }
-            atomicAdd(&a->steps, sum[4]);
+            __hip_atomic_fetch_add(&slots.w[s][8], (unsigned long long)w[8] + ((unsigned long long)(w[10] >> 10) << 26),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
     }
 }
@@ -230,6 +334,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
     ExitEntry<R>* queue = queues[threadIdx.x / kWave];
     uint32_t qh = 0, qn = 0;  // first entry and entries in the wave's queue (wave-uniform)
     const int lane = threadIdx.x & (kWave - 1);
+    if (lane == 0) {
+        NodeSlots& slots = wave_slots();
+        for (int j = 0; j < kSlots; ++j) {
+            slot_store(&slots.key[j], 0ull);
+            for (int i = 0; i < 9; ++i) slot_store(&slots.w[j][i], 0ull);
+            stamp_store(&slots.stamp[j], 0u);
+        }
+        stamp_store(&slots.tick, 0u);
+    }
 
     // wave-uniform pool: node, next path, end, and (per-lane jobs) the job
     uint32_t pool_g = 0, pool_p = 0, pool_end = 0, pool_seg = 0;
@@ -472,6 +585,12 @@ __device__ __forceinline__ void walk_body(const WalkArgs& A)
         drain_exits<R, LANE>(A, queue, qh, c);
         qh = (qh + c) & (kQueue - 1);
         qn -= c;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        NodeSlots& slots = wave_slots();
+        for (uint32_t j = 0; j < (uint32_t)kSlots; ++j)
+            if (slot_load(&slots.key[j]) != 0ull) flush_slot(slots, j);
     }
 }
 

@@ -289,6 +289,33 @@ def test_edge_cases(ctx, ref):
     assert g["capped"] == 0 and np.all(np.isfinite(g["mean"]))
 
 
+def test_many_nodes_per_drain(ctx, ref):
+    """A few paths per node: every pool is a handful of paths, so a wave's
+    exit queue holds many nodes at once and its node slots in LDS are evicted
+    to the node sums over and over.  The sums are exact, so the double walk's
+    means, sums and step totals must still match the oracle path for path,
+    and the float walk must give the same sums with and without per-path
+    records (a different schedule) and across repeated calls."""
+    d = W.random_density(5, 3)
+    bm = {"kind": "affine", "p": [0.3, 2.0, -0.5, -1.0, 0.25, 3.0]}
+    nodes = W.random_nodes(500, 21)
+    for N in (1, 5, 37):
+        g = gpu_estimate(ctx, d, bm, nodes, N, 1e-3, 22, "fp64", per_path=True)
+        r = ref.interface_estimate(d, bm, nodes, N, 1e-3, 22, per_path=True)
+        flips, dmax = compare_paths(g["per_path"], r["per_path"], 1e-12)
+        assert flips.sum() == 0 and dmax <= 1e-12
+        assert np.max(np.abs(g["mean"] - r["mean"])) <= 1e-10
+        assert np.max(np.abs(g["sums"] - r["sums"]) / np.maximum(1.0, np.abs(r["sums"]))) <= 1e-12
+        assert g["steps"] == r["steps"] and g["paths"] == r["paths"] == 500 * N
+    a = gpu_estimate(ctx, d, bm, nodes, 37, 1e-3, 23, "fp32")
+    b = gpu_estimate(ctx, d, bm, nodes, 37, 1e-3, 23, "fp32", per_path=True)
+    c = gpu_estimate(ctx, d, bm, nodes, 37, 1e-3, 23, "fp32")
+    for o in (b, c):
+        assert np.array_equal(a["sums"], o["sums"]) and np.array_equal(a["mean"], o["mean"])
+        assert a["steps"] == o["steps"]
+    assert int(b["per_path"]["steps"].sum()) == b["steps"]
+
+
 def test_more_paths_than_32_bits_and_empty_inputs(ctx, ref):
     """n * N above 2^32 (70 000 nodes x 65 536 paths = 4.59e9 paths; the
     walk's workspace is the 6.7 MB of node sums), every path capped at three
