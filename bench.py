@@ -208,20 +208,24 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
                 print(f"[serve] {len(out)} of {n_requests} requests done, "
                       f"{time.perf_counter() - start:.0f} s", file=sys.stderr, flush=True)
 
+        def shape(r, req):
+            L = req["layout"]
+            r.update(grid=f"{L['nx']}x{L['ny']}", subdomains=f"{L['sx']}x{L['sy']}", nodes=r["n_nodes"])
+            return r
+
         for req, ta in zip(reqs[burst:], arrivals):
             while True:
                 now = time.perf_counter() - start
                 for rid in list(pending):
                     r = srv.poll(rid)
                     if r is not None:
-                        done(r)
-                        del pending[rid]
+                        done(shape(r, pending.pop(rid)))
                 if now >= ta:
                     break
                 time.sleep(min(ta - now, 0.002))
-            pending[srv.submit(req)] = True
+            pending[srv.submit(req)] = req
         for rid in list(pending):
-            done(srv.wait(rid))
+            done(shape(srv.wait(rid), pending[rid]))
         wall = max(r["t_done"] for r in out) - min(r["t_submit"] for r in out)
     finally:
         srv.close()
@@ -239,10 +243,27 @@ def serve_stream(ctx, n_requests: int, load: float, burst: int, seed: int = 4, b
         "capped_paths": int(sum(r["capped"] for r in ok)),
         "stage_ms_median": {k: float(np.median([r[k] for r in ok]))
                             for k in ("t_queue_ms", "t_stoc_ms", "t_fill_ms", "t_sub_ms")},
+        "stage_ms_p99": {k: float(np.percentile([r[k] for r in ok], 99))
+                         for k in ("t_queue_ms", "t_stoc_ms", "t_fill_ms", "t_sub_ms")},
+        "slowest_1pct": slowest(ok, lat),
         "stream": "1-4 Gaussian bumps (amp U[1,20], width U[20,200]), grids {33,65,129,257}^2, 2x2..8x8 "
                   "subdomains, SE 1e-3 per node, float walks, Poisson arrivals, "
                   + (f"bridge exit test at dt {bridge_dt:g}" if bridge_dt > 0 else "end-of-step exit test at dt 1e-4"),
     }
+
+
+def slowest(ok, lat):
+    """The slowest 1% of requests: their shapes and where their time went."""
+    import numpy as np
+    k = max(1, len(ok) // 100)
+    order = np.argsort(lat)[::-1][:k]
+    rows = []
+    for i in order:
+        r = ok[int(i)]
+        rows.append({"latency_ms": round(float(lat[i]), 1),
+                     **{key: r.get(key) for key in ("grid", "subdomains", "nodes", "paths_per_node")},
+                     **{key: round(float(r[key]), 2) for key in ("t_queue_ms", "t_stoc_ms", "t_fill_ms", "t_sub_ms")}})
+    return rows
 
 
 def serve_like(ctx, grid: int = 257, sub: int = 8, paths: int = 65536, dt: float = 1e-4):

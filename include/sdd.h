@@ -39,7 +39,10 @@
  *   - Arrays of points are [n][2] doubles (xi, eta) or (x, y), row-major.
  *   - Environment (tuning only; no result depends on it): SDD_WALK_WAVES_PER_SIMD
  *     and SDD_SERVE_WAVES_PER_SIMD set the waves per SIMD of the walk's and
- *     the server's persistent grids instead of the measured defaults.
+ *     the server's persistent grids instead of the measured defaults;
+ *     SDD_SERVE_RESERVED_CUS (default 0) keeps a server's walk launches off
+ *     that many CUs, read when the server is created, so that its subdomain
+ *     solves find free CUs (lower p99 latency, lower capacity).
  */
 #ifndef SDD_H
 #define SDD_H

@@ -39,6 +39,7 @@ namespace sdd {
 
 constexpr uint32_t kBlockPaths = 1024;  // paths per node in a scheduling block
 constexpr int kMaxSegments = 256;
+constexpr int kServeReservedCUs = 0;  // CUs the walk launches leave free (see sdd_server_create)
 
 // ------------------------------------------------------------------ host
 
@@ -601,13 +602,28 @@ sdd_status sdd_server_create(sdd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_
     S->budget = hbm_budget_bytes;
     bool ok = hipMalloc((void**)&S->arena_base, hbm_budget_bytes) == hipSuccess;
     if (ok) S->arena.init(hbm_budget_bytes);
+    int cus = 0;
+    ok = ok && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0;
+    // CUs the walk streams leave to the finish stream (SDD_SERVE_RESERVED_CUS
+    // overrides): walk launches otherwise hold every CU, and a subdomain
+    // solve block, which needs a CU's worth of free wave slots, waits for a
+    // launch to end.
+    int reserve = kServeReservedCUs;
+    if (const char* env = getenv("SDD_SERVE_RESERVED_CUS")) reserve = atoi(env);
+    if (reserve < 0 || reserve >= cus) reserve = 0;
     for (int i = 0; i < 2 && ok; ++i) {
         ok = hipMalloc((void**)&S->dsegs[i], kMaxSegments * sizeof(WalkSeg)) == hipSuccess &&
              hipMalloc((void**)&S->counter[i], 256) == hipSuccess &&
              hipHostMalloc((void**)&S->hsegs[i], kMaxSegments * sizeof(WalkSeg), hipHostMallocDefault) == hipSuccess &&
-             hipStreamCreateWithFlags(&S->walk_stream[i], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreate(&S->launches[i].ev_start) == hipSuccess &&
              hipEventCreate(&S->launches[i].ev) == hipSuccess;
+        if (ok && reserve > 0) {
+            std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+            for (int c = reserve; c < cus; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+            ok = hipExtStreamCreateWithCUMask(&S->walk_stream[i], (uint32_t)mask.size(), mask.data()) == hipSuccess;
+        } else if (ok) {
+            ok = hipStreamCreateWithFlags(&S->walk_stream[i], hipStreamNonBlocking) == hipSuccess;
+        }
     }
     ok = ok && hipStreamCreateWithFlags(&S->finish_stream, hipStreamNonBlocking) == hipSuccess &&
          hipStreamCreateWithFlags(&S->setup_stream, hipStreamNonBlocking) == hipSuccess &&
@@ -617,9 +633,8 @@ sdd_status sdd_server_create(sdd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_
                      align_up((size_t)max_nodes * 2 * sizeof(double), 256) +
                      align_up((size_t)max_points * 2 * sizeof(double), 256);
     ok = ok && hipHostMalloc((void**)&S->pinned, S->slot_stride * max_slots, hipHostMallocDefault) == hipSuccess;
-    int cus = 0;
     const int occ = ok ? serve_walk_occupancy() : 0;
-    ok = ok && occ > 0 && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess;
+    ok = ok && occ > 0;
     if (!ok) {
         sdd_server_destroy(S);
         return SDD_EDEVICE;
@@ -633,7 +648,7 @@ sdd_status sdd_server_create(sdd_ctx* ctx, size_t hbm_budget_bytes, int32_t max_
     int want = 3;
     if (const char* env = getenv("SDD_SERVE_WAVES_PER_SIMD"))
         if (atoi(env) > 0) want = atoi(env);
-    S->walk_blocks = std::max(1, std::min(occ, want)) * cus;
+    S->walk_blocks = std::max(1, std::min(occ, want)) * (cus - reserve);
     S->pool_paths = pool_paths_for(launch_paths, cus);
     for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
     S->worker = std::thread(worker_loop, S);

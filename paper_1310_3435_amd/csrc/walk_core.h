@@ -247,7 +247,7 @@ __device__ __forceinline__ void drain_exits(const WalkArgs& A, const ExitEntry<R
             for (int j = 0; j < 4; ++j) {
                 // the node's sum of n over these lanes, |t| <= 2^60
                 const long long t = (long long)w[2 * j] + ((long long)w[2 * j + 1] << 26) +
-                                    ((long long)((int)h[j] - 4 * (int)cnt) << 52);
+                                    (long long)((int)h[j] - 4 * (int)cnt) * (1ll << 52);
                 __hip_atomic_fetch_add(&slots.w[s][j], (unsigned long long)(t & 0x7fffffffll), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WAVEFRONT);
                 __hip_atomic_fetch_add(&slots.w[s][4 + j], (unsigned long long)(t >> 31), __ATOMIC_RELAXED,

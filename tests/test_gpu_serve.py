@@ -271,3 +271,23 @@ def test_fixed_path_request_equals_the_estimate_call_bitwise(ctx):
     assert sdd.walk_stats(est["stats"])["steps"] == alone["steps"]
     assert np.array_equal(mesh.cpu().numpy(), alone["mesh"])
     say(f"  5000 -> 5120 paths per node, alone == in a mix == estimate + fill + solve, bitwise")
+
+
+def test_walks_on_fewer_cus_give_the_same_result(ctx, monkeypatch):
+    """SDD_SERVE_RESERVED_CUS keeps the walk launches off some CUs (their
+    streams carry a CU mask), so that subdomain solves find free CUs.  Where
+    the walks run does not change what they compute: same mesh, bitwise."""
+    import paper_1310_3435_amd as sdd
+    req = small_request(seed=29, n=65, s=4, paths=3000, se=0.0)
+    got = []
+    for reserve in ("0", "16"):
+        monkeypatch.setenv("SDD_SERVE_RESERVED_CUS", reserve)
+        srv = sdd.Server(ctx, hbm_budget_bytes=256 << 20, max_slots=8)
+        try:
+            say(f"serve: a fixed-path request with {reserve} CUs left to the solves")
+            got.append(srv.wait(srv.submit(req)))
+        finally:
+            srv.close()
+    a, b = got
+    assert a["status"] == b["status"] == 0
+    assert a["steps"] == b["steps"] and np.array_equal(a["mesh"], b["mesh"])
