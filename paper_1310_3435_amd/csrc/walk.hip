@@ -189,11 +189,14 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
     // over more lanes, and the last, longest paths then leave more lanes
     // idle.  Measured same-box: a single-term kernel runs paths of thousands
     // of steps (dt < 2e-5) 1-4% faster with 3 waves than with 4 (ring,
-    // sin^2, sech^2), shorter paths up to 4.5% faster with 4, and loses 2-4%
-    // with 6 or 8.  The general sum of terms, whose term loop leaves more
-    // latency to hide, runs its 64-VGPR instance with 8 waves on short
-    // paths (19% faster than 4 waves of the full-register one at dt = 1e-4,
-    // 5% slower at 1e-5, where it keeps the full-register one).
+    // sin^2), shorter paths up to 4.5% faster with 4, and loses 2-4% with 6
+    // or 8.  The sech^2 walk with the end-of-step test, whose exit drain
+    // keeps node sums in LDS slots, runs 1.4% faster with 4 (the ring 1.5%
+    // slower), so it takes 4 at any dt.  The general sum of terms, whose
+    // term loop leaves more latency to hide, runs its 64-VGPR instance with
+    // 8 waves on short paths (19% faster than 4 waves of the full-register
+    // one at dt = 1e-4, 5% slower at 1e-5, where it keeps the full-register
+    // one).
     constexpr auto kernel = [] {
         if constexpr (WIDE)
             return walk_kernel_wide<R, KIND, EXIT>;
@@ -216,7 +219,8 @@ static hipError_t launch_walk_kernel(const WalkArgs& A, hipStream_t stream)
         if (env && atoi(env) > 0) G.env = atoi(env);
         return G;
     }();
-    int want = WIDE ? 8 : KIND == kAnyTerms ? 4 : A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one per SIMD
+    constexpr bool kSech2Step = KIND == SDD_TERM_SECH2 && EXIT == kExitStep;
+    int want = WIDE ? 8 : (KIND == kAnyTerms || kSech2Step) ? 4 : A.dt < kLongPathDt ? 3 : 4;  // blocks of 4 waves: one per SIMD
     if (grid.env > 0) want = grid.env;
     const int per_cu_blocks = want < grid.occ ? want : grid.occ;
     // paths to walk, hence waves worth launching
