@@ -138,7 +138,8 @@ __device__ __forceinline__ void stamp_store(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-static_assert(offsetof(NodeAcc, hi) == offsetof(NodeAcc, lo) + 32 && offsetof(NodeAcc, steps) == offsetof(NodeAcc, lo) + 64,
+static_assert(offsetof(NodeAcc, hi) == offsetof(NodeAcc, lo) + 32 &&
+                  offsetof(NodeAcc, steps) == offsetof(NodeAcc, lo) + 64,
               "a node slot's nine words follow NodeAcc's lo, hi, steps");
 
 // Add slot s to its node's sums in device memory and empty it.
